@@ -1,0 +1,167 @@
+"""CPU oracle for the Canonical Hub Labeling -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may
+import this package. The product library never links or calls it.
+
+Thin ctypes wrapper over ``chl_oracle.c`` (plain C, built with gcc). See the
+header of that file for what each function computes and which passage of the
+paper it follows. All labels are returned in input vertex ids; hubs are given
+by their rank position (0 = most important).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "chl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODE_DEFINITION = 0
+MODE_PLANT = 1          # Algorithm 3 with early termination
+MODE_PLANT_FULL = 2     # Algorithm 3 without early termination
+
+
+def build(src=_SRC, out=_LIB, extra=()):
+    """Compile the oracle with gcc into a shared library."""
+    cmd = ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-pthread", *extra, src, "-o", out]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+_lib = None
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def load(path=None):
+    """Load (building first if absent) the oracle library."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    lib_path = path or _LIB
+    if not os.path.exists(lib_path) or (path is None and os.path.getmtime(lib_path) < os.path.getmtime(_SRC)):
+        build(out=lib_path)
+    lib = C.CDLL(lib_path)
+    vp = C.c_void_p
+    lib.oracle_run_roots.restype = vp
+    lib.oracle_run_roots.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int]
+    lib.oracle_run_count.restype = C.c_int64
+    lib.oracle_run_count.argtypes = [vp, C.c_int64]
+    lib.oracle_run_total.restype = C.c_int64
+    lib.oracle_run_total.argtypes = [vp]
+    lib.oracle_run_labels.argtypes = [vp, C.c_int64, vp, vp]
+    lib.oracle_run_stats.argtypes = [vp, vp]
+    lib.oracle_run_assemble.argtypes = [vp, vp, vp, vp]
+    lib.oracle_run_free.argtypes = [vp]
+    lib.oracle_query.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
+    lib.oracle_sssp.argtypes = [C.c_int32, vp, vp, vp, C.c_int32, vp]
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _graph_args(row_ptr, col, w, order):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.int32)
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    return row_ptr, col, w, order
+
+
+class Labels:
+    """Assembled labeling: offsets[n+1], hub_pos[L] (rank positions), dist[L] (int64)."""
+
+    def __init__(self, offsets, hub_pos, dist, stats=None):
+        self.offsets, self.hub_pos, self.dist, self.stats = offsets, hub_pos, dist, stats
+
+    @property
+    def n(self):
+        return len(self.offsets) - 1
+
+    @property
+    def total(self):
+        return int(self.offsets[-1])
+
+    def of(self, v):
+        a, b = self.offsets[v], self.offsets[v + 1]
+        return list(zip(self.hub_pos[a:b].tolist(), self.dist[a:b].tolist()))
+
+
+def chl(row_ptr, col, w, order, mode=MODE_PLANT, threads=None, lib=None):
+    """Complete CHL of the graph under the ranking ``order`` (order[0] most
+    important). Returns ``Labels`` with per-root stats [n_roots, 4] =
+    (settled, arcs, labels, early) indexed by root rank position."""
+    lib = lib or load()
+    row_ptr, col, w, order = _graph_args(row_ptr, col, w, order)
+    n = len(row_ptr) - 1
+    threads = threads or min(16, os.cpu_count() or 1)
+    h = lib.oracle_run_roots(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                             order.ctypes.data, None, 0, mode, threads)
+    try:
+        total = lib.oracle_run_total(h)
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        hub = np.zeros(max(total, 1), dtype=np.int32)
+        dist = np.zeros(max(total, 1), dtype=np.int64)
+        lib.oracle_run_assemble(h, offsets.ctypes.data, hub.ctypes.data, dist.ctypes.data)
+        stats = np.zeros((n, 4), dtype=np.int64)
+        lib.oracle_run_stats(h, stats.ctypes.data)
+    finally:
+        lib.oracle_run_free(h)
+    return Labels(offsets, hub[:total], dist[:total], stats)
+
+
+def roots(row_ptr, col, w, order, root_pos, mode=MODE_PLANT, threads=None, lib=None):
+    """Labels of selected roots (given by rank position). Returns a list of
+    (vertices int32, dists int64) sorted by vertex, one per root, and stats
+    [len(root_pos), 4]."""
+    lib = lib or load()
+    row_ptr, col, w, order = _graph_args(row_ptr, col, w, order)
+    n = len(row_ptr) - 1
+    rp = np.ascontiguousarray(root_pos, dtype=np.int32)
+    threads = threads or min(16, os.cpu_count() or 1)
+    h = lib.oracle_run_roots(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                             order.ctypes.data, rp.ctypes.data, len(rp), mode, threads)
+    out = []
+    try:
+        for t in range(len(rp)):
+            c = lib.oracle_run_count(h, t)
+            v = np.zeros(max(c, 1), dtype=np.int32)
+            d = np.zeros(max(c, 1), dtype=np.int64)
+            lib.oracle_run_labels(h, t, v.ctypes.data, d.ctypes.data)
+            v, d = v[:c], d[:c]
+            s = np.argsort(v, kind="stable")
+            out.append((v[s], d[s]))
+        stats = np.zeros((len(rp), 4), dtype=np.int64)
+        lib.oracle_run_stats(h, stats.ctypes.data)
+    finally:
+        lib.oracle_run_free(h)
+    return out, stats
+
+
+def query(labels, pairs, lib=None):
+    """Distances for int32 pairs [q, 2] by the sorted-list merge; -1 if no common hub."""
+    lib = lib or load()
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(len(pairs), dtype=np.int64)
+    off = np.ascontiguousarray(labels.offsets, dtype=np.int64)
+    hub = np.ascontiguousarray(labels.hub_pos, dtype=np.int32)
+    dist = np.ascontiguousarray(labels.dist, dtype=np.int64)
+    lib.oracle_query(off.ctypes.data, hub.ctypes.data, dist.ctypes.data,
+                     pairs.ctypes.data, len(pairs), out.ctypes.data)
+    return out
+
+
+def sssp(row_ptr, col, w, src, lib=None):
+    """Dijkstra distances from src (int64, -1 unreachable)."""
+    lib = lib or load()
+    row_ptr, col, w, _ = _graph_args(row_ptr, col, w, np.zeros(1, np.int32))
+    n = len(row_ptr) - 1
+    out = np.zeros(n, dtype=np.int64)
+    lib.oracle_sssp(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data, int(src), out.ctypes.data)
+    return out

@@ -1,0 +1,404 @@
+/*
+ * CPU oracle for the Canonical Hub Labeling (CHL) -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load this file's library. It shares no code, header or table with the
+ * HIP library and must never be reached from the product path.
+ *
+ * Everything here is plain, sequential per root, and int64 in distances.
+ * Vertices keep their input ids; the ranking enters only through
+ * pos[v] = rank position (pos[order[i]] = i, 0 = most important), so that
+ * "x outranks y" (R(x) > R(y) in the paper's notation) is pos[x] < pos[y].
+ *
+ * Two independent computations of the labels with hub h (root h):
+ *
+ *  (1) oracle_def_tree -- the definition. A label (h, d(v,h)) belongs to L_v
+ *      exactly when h is the highest ranked vertex of SP_{v,h}, the set of
+ *      vertices on all shortest v-h paths, inclusive (Section 1, CHL of
+ *      Abraham et al. and the notation table; Lemma 1 of Section 3.1 states
+ *      the converse, that any other label is redundant). It runs a complete
+ *      Dijkstra from h, then walks the vertices in order of distance and marks
+ *      v "outranked" when v itself outranks h or some shortest-path
+ *      predecessor p (d(h,p) + w(p,v) = d(h,v)) is outranked; this is the
+ *      recursion SP_{h,v} = {v} U (union over those p of SP_{h,p}).
+ *
+ *  (2) oracle_plant_tree -- the PLaNTDijkstra procedure (Section 4.2,
+ *      Algorithm 3) in the paper's order and notation: distances delta[],
+ *      most-important-ancestor a[], the equal-distance ancestor update, and
+ *      the counter cnt of queued vertices whose ancestor is the root, used
+ *      for early termination. Two readings are taken where the printed
+ *      algorithm is ambiguous:
+ *        - the "skip if an ancestor outranks the root" test skips only the
+ *          label, never the relaxation of the vertex's edges (PLaNT prunes
+ *          labels, not trees: Section 1 and the footnote on early
+ *          termination in Section 4.2);
+ *        - cnt counts queued, not yet popped, vertices whose ancestor is the
+ *          root, and is tested before every pop.
+ *      The heap pops by (distance, rank position); this tie order fixes the
+ *      counted work (vertices settled, arcs scanned) but not the labels.
+ *
+ * oracle_chl() runs one of them for every root (roots handed out to
+ * threads by an atomic counter in rank order, the paper's task queue of
+ * Section 3.1) and assembles L_v sorted by hub rank position, most important
+ * hub first (Algorithm 2's sort step; the query merge of Section 5 relies on
+ * it). oracle_query() answers distance queries by the sorted-list merge of
+ * Section 5 (QLSN): the minimum of d_u + d_v over common hubs, -1 when the
+ * lists share no hub.
+ */
+#include <pthread.h>
+#include <stdatomic.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define INF64 INT64_MAX
+
+/* ---------------- binary heap of (dist, pos, v) ---------------- */
+typedef struct { int64_t d; int32_t p; int32_t v; } hitem;
+typedef struct { hitem* a; int64_t size, cap; } heap_t;
+
+static int hless(const hitem* x, const hitem* y) {
+    return x->d < y->d || (x->d == y->d && x->p < y->p);
+}
+static void hpush(heap_t* h, hitem it) {
+    if (h->size == h->cap) {
+        h->cap = h->cap ? 2 * h->cap : 1024;
+        h->a = (hitem*)realloc(h->a, (size_t)h->cap * sizeof(hitem));
+    }
+    int64_t i = h->size++;
+    while (i > 0) {
+        int64_t par = (i - 1) / 2;
+        if (!hless(&it, &h->a[par])) break;
+        h->a[i] = h->a[par];
+        i = par;
+    }
+    h->a[i] = it;
+}
+static hitem hpop(heap_t* h) {
+    hitem top = h->a[0];
+    hitem last = h->a[--h->size];
+    int64_t i = 0;
+    for (;;) {
+        int64_t c = 2 * i + 1;
+        if (c >= h->size) break;
+        if (c + 1 < h->size && hless(&h->a[c + 1], &h->a[c])) c++;
+        if (!hless(&h->a[c], &last)) break;
+        h->a[i] = h->a[c];
+        i = c;
+    }
+    if (h->size > 0) h->a[i] = last;
+    return top;
+}
+
+/* ---------------- per-thread workspace ---------------- */
+typedef struct {
+    int32_t n;
+    int64_t* dist;      /* delta[] */
+    int32_t* anc;       /* a[] (PLaNT) */
+    uint8_t* settled;
+    uint8_t* outr;      /* outranked flag (definition) */
+    int32_t* touched;   /* vertices whose state left its initial value */
+    int64_t ntouched;
+    int32_t* popped;    /* pop order (definition) */
+    heap_t heap;
+} ws_t;
+
+static ws_t* ws_new(int32_t n) {
+    ws_t* w = (ws_t*)calloc(1, sizeof(ws_t));
+    w->n = n;
+    w->dist = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    w->anc = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    w->settled = (uint8_t*)calloc((size_t)n, 1);
+    w->outr = (uint8_t*)calloc((size_t)n, 1);
+    w->touched = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    w->popped = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    for (int32_t v = 0; v < n; v++) { w->dist[v] = INF64; w->anc[v] = v; }
+    return w;
+}
+static void ws_free(ws_t* w) {
+    free(w->dist); free(w->anc); free(w->settled); free(w->outr);
+    free(w->touched); free(w->popped); free(w->heap.a); free(w);
+}
+/* restore every touched entry to its initial value (sparse re-initialisation) */
+static void ws_reset(ws_t* w) {
+    for (int64_t i = 0; i < w->ntouched; i++) {
+        int32_t v = w->touched[i];
+        w->dist[v] = INF64; w->anc[v] = v; w->settled[v] = 0; w->outr[v] = 0;
+    }
+    w->ntouched = 0;
+    w->heap.size = 0;
+}
+
+typedef struct { int64_t settled, arcs, labels; int32_t early; } tree_stats;
+
+/* (1) definition: labels with hub h. out_v/out_d receive the labelled
+ * vertices and distances (capacity n). Returns the label count. */
+int64_t oracle_def_tree(ws_t* w, const int64_t* row_ptr, const int32_t* col,
+                        const int32_t* wt, const int32_t* pos, int32_t h,
+                        int32_t* out_v, int64_t* out_d, tree_stats* st) {
+    int64_t npop = 0, arcs = 0;
+    w->dist[h] = 0; w->touched[w->ntouched++] = h;
+    hpush(&w->heap, (hitem){0, pos[h], h});
+    while (w->heap.size) {                       /* plain Dijkstra, no pruning */
+        hitem it = hpop(&w->heap);
+        int32_t v = it.v;
+        if (w->settled[v] || it.d != w->dist[v]) continue;
+        w->settled[v] = 1;
+        w->popped[npop++] = v;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t u = col[e];
+            int64_t nd = it.d + wt[e];
+            arcs++;
+            if (nd < w->dist[u]) {
+                if (w->dist[u] == INF64) w->touched[w->ntouched++] = u;
+                w->dist[u] = nd;
+                hpush(&w->heap, (hitem){nd, pos[u], u});
+            }
+        }
+    }
+    int64_t nl = 0;
+    for (int64_t i = 0; i < npop; i++) {         /* non-decreasing distance */
+        int32_t v = w->popped[i];
+        uint8_t o = pos[v] < pos[h];
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1] && !o; e++) {
+            int32_t p = col[e];
+            if (w->dist[p] != INF64 && w->dist[p] + wt[e] == w->dist[v]) o |= w->outr[p];
+        }
+        w->outr[v] = o;
+        if (!o) { out_v[nl] = v; out_d[nl] = w->dist[v]; nl++; }
+    }
+    if (st) { st->settled = npop; st->arcs = arcs; st->labels = nl; st->early = 0; }
+    ws_reset(w);
+    return nl;
+}
+
+/* argmax of R over {x, y}: the one with the smaller rank position */
+static inline int32_t top_of(const int32_t* pos, int32_t x, int32_t y) {
+    return pos[x] < pos[y] ? x : y;
+}
+
+/* (2) PLaNTDijkstra (Algorithm 3) with the readings stated above. */
+int64_t oracle_plant_tree(ws_t* w, const int64_t* row_ptr, const int32_t* col,
+                          const int32_t* wt, const int32_t* pos, int32_t h,
+                          int early_term, int32_t* out_v, int64_t* out_d,
+                          tree_stats* st) {
+    int64_t* delta = w->dist;
+    int32_t* a = w->anc;
+    int64_t nl = 0, npop = 0, arcs = 0, cnt;
+    int32_t stopped = 0;
+    delta[h] = 0; a[h] = h; w->touched[w->ntouched++] = h;
+    hpush(&w->heap, (hitem){0, pos[h], h});
+    cnt = 1;
+    while (w->heap.size) {
+        if (early_term && cnt == 0) { stopped = 1; break; }   /* early termination */
+        hitem it = hpop(&w->heap);
+        int32_t v = it.v;
+        if (w->settled[v] || it.d != delta[v]) continue;     /* stale queue entry */
+        w->settled[v] = 1;
+        npop++;
+        int32_t nA = top_of(pos, v, a[v]);
+        if (a[v] == h) cnt--;
+        if (!(pos[nA] < pos[h])) {                           /* R[nA] > R[h] skips the label only */
+            out_v[nl] = v; out_d[nl] = delta[v]; nl++;
+        }
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+            int32_t u = col[e];
+            int64_t nd = delta[v] + wt[e];
+            int32_t pA = a[u];
+            arcs++;
+            if (nd < delta[u]) a[u] = top_of(pos, nA, u);
+            else if (nd == delta[u]) a[u] = top_of(pos, nA, pA);
+            if (a[u] == h && pA != h) cnt++;
+            else if (a[u] != h && pA == h) cnt--;
+            if (nd < delta[u]) {
+                if (delta[u] == INF64) w->touched[w->ntouched++] = u;
+                delta[u] = nd;
+                hpush(&w->heap, (hitem){nd, pos[u], u});
+            }
+        }
+    }
+    if (st) { st->settled = npop; st->arcs = arcs; st->labels = nl; st->early = stopped && w->heap.size > 0; }
+    ws_reset(w);
+    return nl;
+}
+
+/* ---------------- whole-labeling driver ---------------- */
+typedef struct {
+    int32_t n;
+    const int64_t* row_ptr; const int32_t* col; const int32_t* wt;
+    int32_t* pos; const int32_t* order;
+    int mode;                       /* 0 definition, 1 PLaNT + early term, 2 PLaNT without */
+    const int32_t* roots; int64_t nroots;   /* root rank positions to run */
+    _Atomic int64_t next;
+    int32_t** lv; int64_t** ld; int64_t* cnt;  /* per task (index into roots) */
+    tree_stats* stats;
+} job_t;
+
+static void* worker(void* arg) {
+    job_t* J = (job_t*)arg;
+    ws_t* w = ws_new(J->n);
+    int32_t* bv = (int32_t*)malloc((size_t)J->n * sizeof(int32_t));
+    int64_t* bd = (int64_t*)malloc((size_t)J->n * sizeof(int64_t));
+    for (;;) {
+        int64_t t = atomic_fetch_add(&J->next, 1);
+        if (t >= J->nroots) break;
+        int32_t h = J->order[J->roots[t]];
+        tree_stats st;
+        int64_t nl = J->mode == 0
+            ? oracle_def_tree(w, J->row_ptr, J->col, J->wt, J->pos, h, bv, bd, &st)
+            : oracle_plant_tree(w, J->row_ptr, J->col, J->wt, J->pos, h, J->mode == 1, bv, bd, &st);
+        J->lv[t] = (int32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(int32_t));
+        J->ld[t] = (int64_t*)malloc((size_t)(nl ? nl : 1) * sizeof(int64_t));
+        memcpy(J->lv[t], bv, (size_t)nl * sizeof(int32_t));
+        memcpy(J->ld[t], bd, (size_t)nl * sizeof(int64_t));
+        J->cnt[t] = nl;
+        J->stats[t] = st;
+    }
+    free(bv); free(bd); ws_free(w);
+    return NULL;
+}
+
+typedef struct {
+    int32_t n; int64_t nroots;
+    int32_t* roots;                  /* root rank positions, in task order */
+    int32_t** lv; int64_t** ld; int64_t* cnt;
+    tree_stats* stats;
+} oracle_run;
+
+static int32_t* make_pos(int32_t n, const int32_t* order) {
+    int32_t* pos = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    for (int32_t i = 0; i < n; i++) pos[order[i]] = i;
+    return pos;
+}
+
+/* Run the trees of the given root rank positions (roots == NULL: all, in
+ * rank order). Returns a handle holding per-root labels and statistics. */
+oracle_run* oracle_run_roots(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                             const int32_t* wt, const int32_t* order,
+                             const int32_t* roots, int64_t nroots, int mode,
+                             int nthreads) {
+    oracle_run* R = (oracle_run*)calloc(1, sizeof(oracle_run));
+    R->n = n;
+    if (!roots) nroots = n;
+    R->nroots = nroots;
+    R->roots = (int32_t*)malloc((size_t)(nroots ? nroots : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < nroots; i++) R->roots[i] = roots ? roots[i] : (int32_t)i;
+    R->lv = (int32_t**)calloc((size_t)(nroots ? nroots : 1), sizeof(int32_t*));
+    R->ld = (int64_t**)calloc((size_t)(nroots ? nroots : 1), sizeof(int64_t*));
+    R->cnt = (int64_t*)calloc((size_t)(nroots ? nroots : 1), sizeof(int64_t));
+    R->stats = (tree_stats*)calloc((size_t)(nroots ? nroots : 1), sizeof(tree_stats));
+    job_t J = {0};
+    J.n = n; J.row_ptr = row_ptr; J.col = col; J.wt = wt; J.order = order;
+    J.pos = make_pos(n, order); J.mode = mode; J.roots = R->roots; J.nroots = nroots;
+    atomic_init(&J.next, 0);
+    J.lv = R->lv; J.ld = R->ld; J.cnt = R->cnt; J.stats = R->stats;
+    if (nthreads < 1) nthreads = 1;
+    pthread_t* th = (pthread_t*)malloc((size_t)nthreads * sizeof(pthread_t));
+    for (int i = 0; i < nthreads; i++) pthread_create(&th[i], NULL, worker, &J);
+    for (int i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
+    free(th); free(J.pos);
+    return R;
+}
+
+int64_t oracle_run_count(const oracle_run* R, int64_t t) { return R->cnt[t]; }
+
+int64_t oracle_run_total(const oracle_run* R) {
+    int64_t s = 0;
+    for (int64_t t = 0; t < R->nroots; t++) s += R->cnt[t];
+    return s;
+}
+
+/* labels of task t: vertices and distances, in the order the tree emitted them */
+void oracle_run_labels(const oracle_run* R, int64_t t, int32_t* v, int64_t* d) {
+    memcpy(v, R->lv[t], (size_t)R->cnt[t] * sizeof(int32_t));
+    memcpy(d, R->ld[t], (size_t)R->cnt[t] * sizeof(int64_t));
+}
+
+/* per task: settled, arcs, labels, early-terminated flag (4 int64 each) */
+void oracle_run_stats(const oracle_run* R, int64_t* out) {
+    for (int64_t t = 0; t < R->nroots; t++) {
+        out[4 * t + 0] = R->stats[t].settled;
+        out[4 * t + 1] = R->stats[t].arcs;
+        out[4 * t + 2] = R->stats[t].labels;
+        out[4 * t + 3] = R->stats[t].early;
+    }
+}
+
+/* Assemble L_v for every vertex v (input ids): offsets[n+1], hub rank
+ * positions and distances, each L_v sorted by hub rank position. Tasks are
+ * visited in increasing root rank position, so appending keeps every L_v
+ * sorted. Only meaningful for a run over all roots. */
+void oracle_run_assemble(const oracle_run* R, int64_t* offsets, int32_t* hub_pos,
+                         int64_t* dist) {
+    int32_t n = R->n;
+    int64_t* fill = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t* byroot = (int64_t*)malloc((size_t)(R->nroots ? R->nroots : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < R->nroots; i++) byroot[i] = -1;
+    for (int64_t t = 0; t < R->nroots; t++) byroot[R->roots[t]] = t;
+    memset(offsets, 0, ((size_t)n + 1) * sizeof(int64_t));
+    for (int64_t t = 0; t < R->nroots; t++)
+        for (int64_t i = 0; i < R->cnt[t]; i++) offsets[R->lv[t][i] + 1]++;
+    for (int32_t v = 0; v < n; v++) offsets[v + 1] += offsets[v];
+    for (int64_t p = 0; p < R->nroots; p++) {
+        int64_t t = byroot[p];
+        if (t < 0) continue;
+        for (int64_t i = 0; i < R->cnt[t]; i++) {
+            int32_t v = R->lv[t][i];
+            int64_t k = offsets[v] + fill[v]++;
+            hub_pos[k] = (int32_t)p;
+            dist[k] = R->ld[t][i];
+        }
+    }
+    free(fill); free(byroot);
+}
+
+void oracle_run_free(oracle_run* R) {
+    if (!R) return;
+    for (int64_t t = 0; t < R->nroots; t++) { free(R->lv[t]); free(R->ld[t]); }
+    free(R->lv); free(R->ld); free(R->cnt); free(R->stats); free(R->roots); free(R);
+}
+
+/* ---------------- queries ---------------- */
+/* Sorted-list merge over the two label lists (Section 5, QLSN). */
+static int64_t merge_query(const int64_t* off, const int32_t* hub, const int64_t* dist,
+                           int32_t u, int32_t v) {
+    int64_t i = off[u], ie = off[u + 1], j = off[v], je = off[v + 1];
+    int64_t best = -1;
+    while (i < ie && j < je) {
+        if (hub[i] < hub[j]) i++;
+        else if (hub[i] > hub[j]) j++;
+        else {
+            int64_t s = dist[i] + dist[j];
+            if (best < 0 || s < best) best = s;
+            i++; j++;
+        }
+    }
+    return best;
+}
+
+void oracle_query(const int64_t* offsets, const int32_t* hub_pos, const int64_t* dist,
+                  const int32_t* pairs, int64_t q, int64_t* out) {
+    for (int64_t k = 0; k < q; k++)
+        out[k] = merge_query(offsets, hub_pos, dist, pairs[2 * k], pairs[2 * k + 1]);
+}
+
+/* Plain Dijkstra distances from src; -1 for unreachable vertices. */
+void oracle_sssp(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                 const int32_t* wt, int32_t src, int64_t* out) {
+    heap_t hp = {0};
+    uint8_t* done = (uint8_t*)calloc((size_t)n, 1);
+    for (int32_t v = 0; v < n; v++) out[v] = INF64;
+    out[src] = 0;
+    hpush(&hp, (hitem){0, 0, src});
+    while (hp.size) {
+        hitem it = hpop(&hp);
+        if (done[it.v] || it.d != out[it.v]) continue;
+        done[it.v] = 1;
+        for (int64_t e = row_ptr[it.v]; e < row_ptr[it.v + 1]; e++) {
+            int64_t nd = it.d + wt[e];
+            if (nd < out[col[e]]) { out[col[e]] = nd; hpush(&hp, (hitem){nd, 0, col[e]}); }
+        }
+    }
+    for (int32_t v = 0; v < n; v++) if (out[v] == INF64) out[v] = -1;
+    free(done); free(hp.a);
+}

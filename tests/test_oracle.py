@@ -1,0 +1,118 @@
+"""The CPU oracle against what the paper and the mathematics fix: brute force
+on tiny graphs, closed forms, the worked tie example and the counterexample
+for the reading of Algorithm 3 (see tests/pins.py)."""
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import pins
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return oracle.load()
+
+
+def test_fig1_example(lib):
+    pins.check_golden(lib, "fig1_example.txt")
+
+
+def test_reading1_counterexample(lib):
+    pins.check_golden(lib, "reading1_counterexample.txt")
+    n, order, edges, _ = pins.load_golden("reading1_counterexample.txt")
+    row, col, w = pins.csr_from_edges(n, edges)
+    lab = oracle.chl(row, col, w, order, lib=lib)
+    # h = vertex 1, u = vertex 4: no label, distance 2 through x
+    assert all(h != 1 for h, _ in lab.of(4))
+    assert oracle.query(lab, np.array([[1, 4]], np.int32), lib=lib)[0] == 2
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_bruteforce_ties(lib, seed):
+    n = 12 + seed % 30
+    lab, D, order = pins.check_bruteforce(lib, n, int(n * 1.6), 1 + seed % 3, seed)
+    if seed % 4 == 0:
+        pins.check_minimal(lib, lab, D, seed)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_bruteforce_degree_rank(lib, seed):
+    pins.check_bruteforce(lib, 50, 110, 4, 1000 + seed, rank="degree")
+
+
+def test_bruteforce_disconnected(lib):
+    # sparse: several components and isolated vertices
+    for s in range(5):
+        lab, D, _ = pins.check_bruteforce(lib, 40, 25, 5, 77 + s)
+        assert (D >= pins.INF).any()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_closed_forms(lib, seed):
+    pins.check_path(lib, 20 + seed, seed)
+    pins.check_star(lib, 9 + seed, seed)
+    pins.check_complete(lib, 8 + seed, seed)
+    pins.check_unit_grid(lib, 5 + seed, 6, seed)
+    pins.check_even_cycle(lib, 4 + seed, seed)
+    pins.check_tree(lib, 25 + seed, seed)
+
+
+def test_sssp(lib):
+    pins.check_sssp(lib, 3)
+
+
+def test_top_root_is_full_dijkstra(lib):
+    """The most important vertex outranks everybody, so its labels are the
+    Dijkstra distances to its whole component."""
+    c = gg.make_config("grid64")
+    out, _ = oracle.roots(c["row_ptr"], c["col"], c["w"], c["order"], [0], lib=lib)
+    v, d = out[0]
+    ref = oracle.sssp(c["row_ptr"], c["col"], c["w"], int(c["order"][0]), lib=lib)
+    assert np.array_equal(v, np.nonzero(ref >= 0)[0])
+    assert np.array_equal(d, ref[ref >= 0])
+
+
+def test_modes_agree_grid64(lib):
+    c = gg.make_config("grid64")
+    labs = pins.all_modes(c["row_ptr"], c["col"], c["w"], c["order"], lib)
+    for l in labs[1:]:
+        assert np.array_equal(l.offsets, labs[0].offsets)
+        assert np.array_equal(l.hub_pos, labs[0].hub_pos)
+        assert np.array_equal(l.dist, labs[0].dist)
+    # early termination does strictly less work than the full trees
+    assert labs[1].stats[:, 1].sum() < labs[2].stats[:, 1].sum()
+
+
+def test_unique_witness_grid64(lib):
+    """Lemma 2: for every label (h, d) in L_v the merge of L_v and L_h reaches
+    d only at hub h (a second minimiser would be a higher-ranked vertex of
+    SP_{v,h}). Checked on a sample of labels of the 64x64 grid."""
+    c = gg.make_config("grid64")
+    lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], lib=lib)
+    g = np.random.default_rng(5)
+    for k in g.choice(lab.total, 3000, replace=False):
+        v = int(np.searchsorted(lab.offsets, k, side="right") - 1)
+        hp, d = int(lab.hub_pos[k]), int(lab.dist[k])
+        h = int(c["order"][hp])
+        Lv = dict(lab.of(v))
+        Lh = dict(lab.of(h))
+        mins = [x for x in Lv if x in Lh and Lv[x] + Lh[x] == d]
+        assert mins == [hp]
+
+
+def test_queries_match_dijkstra_grid64(lib):
+    c = gg.make_config("grid64")
+    lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], lib=lib)
+    pairs = c["pairs"][:2000]
+    q = oracle.query(lab, pairs, lib=lib)
+    for s in np.unique(pairs[:50, 0]):
+        ref = oracle.sssp(c["row_ptr"], c["col"], c["w"], int(s), lib=lib)
+        sel = pairs[:, 0] == s
+        assert np.array_equal(q[sel], ref[pairs[sel, 1]])
+    assert (q[pairs[:, 0] == pairs[:, 1]] == 0).all()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_work_counts(lib, seed):
+    pins.check_stats(lib, 18 + seed, 30 + 2 * seed, 1 + seed % 3, 300 + seed)
