@@ -1,0 +1,234 @@
+/*
+ * chl.h -- C-ABI of the MI355X (gfx950) library that builds and queries the
+ * Canonical Hub Labeling (CHL) with PLaNT trees.
+ *
+ * Paper: "Planting Trees for scalable and efficient Canonical Hub Labeling"
+ * (arXiv 1907.00140). Definitions used throughout:
+ *   - hub label (h, d(v,h)) of vertex v, label set L_v, cover property and
+ *     distance query by common hubs: Section 1;
+ *   - ranking R, the canonical labeling (only the highest ranked vertex of a
+ *     shortest path becomes the hub of its two ends): Section 1;
+ *   - PLaNT trees (one shortest-path tree per root, labels emitted only where
+ *     no vertex of any shortest root-v path outranks the root, early
+ *     termination once every queued vertex is outranked): Section 4.2,
+ *     Algorithm 3;
+ *   - label sets sorted by hub rank and the sorted-list merge query (QLSN):
+ *     Algorithm 2's sort step and Section 5.
+ *
+ * Conventions shared by every call:
+ *   - The graph is undirected with positive int32 edge weights, given as a
+ *     symmetric CSR; ids are 0..n-1 ("input ids").
+ *   - The ranking is a permutation order[0..n-1]; order[0] is the most
+ *     important vertex. The rank position of v is pos(v), with order[pos(v)]
+ *     = v. Hubs are reported by rank position ("hub_pos"), so L_v is sorted
+ *     by hub_pos ascending = most important hub first. chl_labels_hub_vertex
+ *     maps hub_pos back to input ids.
+ *   - Every L_v contains its own label (pos(v), 0).
+ *   - Pointers are device pointers unless a parameter says otherwise; all
+ *     device work is queued on `stream` (a hipStream_t; NULL = the null
+ *     stream). Calls that return a value computed on the device synchronise
+ *     that stream before returning.
+ *   - Return value: CHL_OK (0) or a negative CHL_ERR_* code. No exception
+ *     crosses this boundary. Output parameters are written only on success.
+ *   - Calls on distinct handles may run concurrently from different host
+ *     threads. A handle must not be freed while another call uses it.
+ */
+#ifndef CHL_H
+#define CHL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define CHL_OK 0
+#define CHL_ERR_INVALID_ARG (-1)    /* bad sizes, CSR, ranking, weights, ids or options */
+#define CHL_ERR_OOM (-2)            /* the allocator returned NULL */
+#define CHL_ERR_HIP (-3)            /* a HIP runtime call failed */
+#define CHL_ERR_DIST_OVERFLOW (-4)  /* a label distance does not fit in int32 */
+#define CHL_ERR_NO_DEVICE (-5)      /* no usable gfx950 device */
+#define CHL_ERR_BUSY (-6)           /* server: request rejected (budget or queue full) */
+
+/* Text for an error code; never NULL, static storage. */
+const char* chl_error_string(int code);
+
+/* ---- graph view ----
+ * Symmetric CSR of an undirected graph (Section 1: G(V, E, W), positive
+ * weights). All arrays are device memory, borrowed for the duration of the
+ * call (they must stay valid until the call returns).
+ *   row_ptr[n+1]: int64, row_ptr[0] = 0, non-decreasing, row_ptr[n] = n_arcs
+ *   col[n_arcs] : int32 neighbour ids in [0, n)
+ *   w[n_arcs]   : int32 weights >= 1
+ * The arc multiset must be symmetric: every arc (v, u, w) has a matching
+ * (u, v, w). Parallel arcs are allowed (the smallest weight decides the
+ * distance); self-loops are allowed and have no effect.
+ * Requirements checked by chl_build (CHL_ERR_INVALID_ARG otherwise):
+ * 1 <= n <= 2^31 - 2, 0 <= n_arcs <= 2^32 - 1, and all of the above. */
+typedef struct chl_graph {
+    int32_t n;
+    int64_t n_arcs;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const int32_t* w;
+} chl_graph;
+
+/* ---- device memory allocator ----
+ * Every device buffer the library keeps or uses as scratch is obtained from
+ * alloc(bytes, ctx) and returned with free(ptr, ctx). alloc returns NULL on
+ * failure (the call then fails with CHL_ERR_OOM and frees what it took).
+ * Passing NULL for the allocator selects hipMalloc / hipFree. The allocator
+ * must stay valid until every handle created with it has been freed. */
+typedef struct chl_allocator {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} chl_allocator;
+
+/* ---- build options ---- */
+#define CHL_MODE_BATCHED 0  /* persistent kernel: one workgroup per tree,
+                               roots_in_flight trees at once, roots taken from
+                               a rank-ordered work queue */
+#define CHL_MODE_PLAIN 1    /* one root per launch; the whole device grows that
+                               single tree (rank order, one tree at a time) */
+
+typedef struct chl_build_opts {
+    int32_t mode;            /* CHL_MODE_BATCHED or CHL_MODE_PLAIN */
+    int32_t roots_in_flight; /* batched: trees in flight (= workgroups); 0 = tuned */
+    int32_t wg_size;         /* 256, 512 or 1024 threads; 0 = tuned */
+    int64_t delta;           /* bucket width of the delta-stepping frontier; 0 = tuned */
+    int32_t early_term;      /* 1: stop a tree once no queued vertex is clean
+                                (Section 4.2, early termination); 0: grow every
+                                tree over its whole component. Same labels. */
+    int32_t stats;           /* 1: keep per-root statistics (chl_build_stats) */
+    int32_t autotune;        /* 1: parameters left at 0 are chosen by timing a
+                                probe set of roots (cached per graph signature);
+                                0: they take fixed defaults */
+    int32_t reserved;
+} chl_build_opts;
+
+/* Defaults: batched, everything tuned, early termination on, stats on. */
+void chl_build_opts_default(chl_build_opts* opts);
+
+/* Opaque labeling handle (device resident). */
+typedef struct chl_labels chl_labels;
+
+/* Build the canonical labeling of graph g under ranking order[] (device
+ * int32[n], order[0] most important, must be a permutation of 0..n-1).
+ * opts may be NULL (defaults). On success *out receives a handle that the
+ * caller owns and releases with chl_labels_free. Synchronises `stream`.
+ * Errors: CHL_ERR_INVALID_ARG (see chl_graph; also order not a permutation,
+ * bad options), CHL_ERR_OOM, CHL_ERR_HIP, CHL_ERR_DIST_OVERFLOW (some label
+ * distance is >= 2^31 - 1), CHL_ERR_NO_DEVICE. */
+int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
+              const chl_allocator* alloc, void* stream, chl_labels** out);
+
+/* Number of vertices and total number of labels (host outputs). */
+int chl_labels_info(const chl_labels* h, int32_t* n, int64_t* total);
+
+/* Copy the labeling out: offsets[n+1] (int64; L_v is entries
+ * offsets[v]..offsets[v+1]-1, v an input id), hub_pos[total] (int32 rank
+ * positions, strictly increasing within each L_v) and dist[total] (int32).
+ * Any output pointer may be NULL to skip it. to_host = 1: outputs are host
+ * memory (the call synchronises `stream`); 0: device memory (asynchronous). */
+int chl_labels_export(const chl_labels* h, int64_t* offsets, int32_t* hub_pos,
+                      int32_t* dist, int to_host, void* stream);
+
+/* hub_vertex[p] = input id of the vertex at rank position p (= order[p]),
+ * int32[n]; host or device output as for chl_labels_export. */
+int chl_labels_hub_vertex(const chl_labels* h, int32_t* hub_vertex, int to_host, void* stream);
+
+/* Point-to-point shortest distance queries by sorted-list merge of the two
+ * label sets (Section 5, single-copy mode): pairs[2q] = (u0, v0, u1, v1, ...)
+ * int32 input ids on the device; out[q] int64 on the device receives
+ * d(u,v), 0 when u == v, -1 when u and v are in different components.
+ * q = 0 is a no-op. Synchronises `stream` (ids are validated on the device);
+ * an id outside [0, n) gives CHL_ERR_INVALID_ARG (out is then unspecified). */
+int chl_query(const chl_labels* h, const int32_t* pairs, int64_t q, int64_t* out, void* stream);
+
+/* ---- statistics ---- */
+typedef struct chl_stats {
+    int64_t n;               /* vertices (= roots) */
+    int64_t labels;          /* total labels */
+    int64_t settled;         /* vertex relaxations performed (a vertex relaxed
+                                again after its key dropped counts again) */
+    int64_t arcs;            /* arcs relaxed */
+    int64_t early_trees;     /* trees that stopped with vertices still queued */
+    int64_t key_bits;        /* 32 or 64: width of the packed (distance, clean) key */
+    int64_t roots_in_flight; /* parameters actually used */
+    int64_t wg_size;
+    int64_t delta;
+    int64_t launches;        /* kernel launches of the tree phase */
+    double tree_ms;          /* device time of the tree phase */
+    double assemble_ms;      /* device time of label assembly */
+    double prep_ms;          /* validation + rank renumbering */
+    double tune_ms;          /* autotuner probe time (0 when cached or off) */
+} chl_stats;
+
+/* Totals into *totals (host, may be NULL). per_root (may be NULL) receives
+ * int64[n][4] = (settled, arcs, labels, early) indexed by root rank position;
+ * host or device as for chl_labels_export. Per-root data needs opts.stats=1,
+ * otherwise CHL_ERR_INVALID_ARG is returned when per_root is not NULL. */
+int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root,
+                    int to_host, void* stream);
+
+/* Release a handle and its device memory (NULL is a no-op). */
+void chl_labels_free(chl_labels* h);
+
+/* ---- continuous-batching server ----
+ * A host thread that owns device streams, keeps labelings resident, batches
+ * distance queries that have arrived and admits build requests by their
+ * device-memory footprint, so that queries and builds overlap on the device.
+ * Times are seconds on the server's clock, which starts at chl_server_start.
+ * Latency of a request = completion time - scheduled arrival time. */
+typedef struct chl_server chl_server;
+
+typedef struct chl_server_opts {
+    size_t mem_budget;          /* bytes of device memory builds may hold at once */
+    int32_t max_batch;          /* max queries per device batch */
+    int32_t build_streams;      /* concurrent builds (streams) */
+    int32_t build_wg;           /* workgroups a build may occupy (caps its share) */
+    int32_t reserved;
+} chl_server_opts;
+
+void chl_server_opts_default(chl_server_opts* o);
+int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_server** out);
+
+/* Register a resident labeling for queries; returns its graph id (>= 0) in
+ * *graph_id. The server does not take ownership. */
+int chl_server_add_labels(chl_server* s, const chl_labels* h, int32_t* graph_id);
+
+/* Schedule q queries against graph_id: host arrays pairs[2q] (input ids) and
+ * t_arrival[q] (non-decreasing seconds). Results go to host out[q] (int64)
+ * and per-query latency to host lat[q] (seconds); both must stay valid until
+ * chl_server_wait returns. */
+int chl_server_submit_queries(chl_server* s, int32_t graph_id, const int32_t* pairs,
+                              const double* t_arrival, int64_t q, int64_t* out, double* lat);
+
+/* Schedule a build of a host-side graph (host CSR arrays, copied at submit)
+ * arriving at t_arrival. On completion the labeling is registered (its graph
+ * id written to *graph_id) and its latency to *lat. *status receives the
+ * build's return code (CHL_ERR_BUSY when its footprint exceeds the whole
+ * budget). */
+int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int64_t* row_ptr,
+                            const int32_t* col, const int32_t* w, const int32_t* order,
+                            double t_arrival, int32_t* graph_id, double* lat, int32_t* status);
+
+/* Start the clock and the dispatch thread; returns immediately. */
+int chl_server_start(chl_server* s);
+
+/* Block until every submitted request has completed. */
+int chl_server_wait(chl_server* s);
+
+/* Labeling produced by a completed build (owned by the server). */
+const chl_labels* chl_server_labels(chl_server* s, int32_t graph_id);
+
+/* Stop the thread and free everything the server owns. */
+void chl_server_destroy(chl_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHL_H */

@@ -1,0 +1,9 @@
+"""PLaNT construction of the Canonical Hub Labeling on MI355X (gfx950).
+
+The work runs in libchl.so (hand-written HIP kernels behind the C-ABI of
+include/chl.h); ``chl`` is its Python binding. Build the library with
+``python -m paper_1907_00140_amd.build``.
+"""
+from .chl import (ChlError, Labels, TorchAllocator, build, load)  # noqa: F401
+
+__all__ = ["ChlError", "Labels", "TorchAllocator", "build", "load"]

@@ -1,0 +1,674 @@
+// Host runtime behind the C-ABI of include/chl.h: argument checks, device
+// validation and rank renumbering, the two tree drivers (batched persistent
+// kernel, plain one-root-per-launch), growth of the label pool, label
+// assembly, queries, statistics and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+
+using namespace chl;
+
+namespace {
+
+void* dflt_alloc(size_t b, void*) {
+    void* p = nullptr;
+    return hipMalloc(&p, b) == hipSuccess ? p : nullptr;
+}
+void dflt_free(void* p, void*) { (void)hipFree(p); }
+
+const chl_allocator kDefaultAlloc = {dflt_alloc, dflt_free, nullptr};
+
+// Allocations of one call; everything not released is freed on exit.
+struct Arena {
+    chl_allocator a;
+    std::vector<void*> ptrs;
+    bool oom = false;
+    explicit Arena(const chl_allocator& al) : a(al) {}
+    template <typename T>
+    T* get(size_t count) {
+        size_t bytes = std::max<size_t>(count * sizeof(T), 256);
+        void* p = a.alloc(bytes, a.ctx);
+        if (!p) { oom = true; return nullptr; }
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+    void drop(void* p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) { a.free(p, a.ctx); ptrs.erase(it); }
+    }
+    void release(void* p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) ptrs.erase(it);
+    }
+    ~Arena() {
+        for (void* p : ptrs) a.free(p, a.ctx);
+    }
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return CHL_ERR_HIP; \
+    } while (0)
+#define OOMCHK(p)                     \
+    do {                              \
+        if (!(p)) return CHL_ERR_OOM; \
+    } while (0)
+
+int check_device() {
+    static int cached = 1;  // 1 = unknown
+    if (cached != 1) return cached;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CHL_ERR_NO_DEVICE;
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return CHL_ERR_NO_DEVICE;
+    cached = std::strncmp(pr.gcnArchName, "gfx950", 6) == 0 ? 0 : CHL_ERR_NO_DEVICE;
+    return cached;
+}
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        (void)hipEventRecord(a, s);
+    }
+    double stop() {
+        float ms = 0;
+        (void)hipEventRecord(b, s);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&ms, a, b);
+        return ms;
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+};
+
+// ---------------------------------------------------------------- tuning
+struct TuneKey {
+    int32_t n;
+    int64_t m;
+    int32_t maxw;
+    int mode;
+    uint64_t sig;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(n, m, maxw, mode, sig) < std::tie(o.n, o.m, o.maxw, o.mode, o.sig);
+    }
+};
+struct TuneVal {
+    int k, wg;
+    int64_t delta;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+// Device state shared by one build.
+struct Build {
+    int32_t n = 0;
+    int64_t m = 0;
+    int key_bits = 32;
+    int32_t maxw = 1;
+    RGraph g{};
+    // control words
+    int32_t* ctl32 = nullptr;          // [0] next_root [1] stop [2] nfailed [3] err
+    unsigned long long* ctl64 = nullptr;  // [0] pool cursor [1] first failed base
+    int32_t* failed = nullptr;         // [n]
+    int32_t* roots = nullptr;          // [n] root list for resumed / probe runs
+    int32_t* far2 = nullptr;           // [n] plain form
+    int32_t* gstate = nullptr;         // plain form state words
+    Pool pool{};
+    int64_t* stats = nullptr;
+};
+
+size_t slot_bytes(int32_t n, int key_bits) {
+    return (size_t)n * (key_bits / 8 + 4 + 12) + (size_t)((n + 7) / 8) * 4;
+}
+
+int alloc_slots(Arena& A, Build& B, int k, Slots& s, hipStream_t st) {
+    s.k = k;
+    s.stride = B.n;
+    s.fstride = (B.n + 7) / 8;
+    size_t kb = (size_t)B.key_bits / 8;
+    s.key = A.get<uint8_t>((size_t)k * B.n * kb);
+    s.flags = A.get<uint32_t>((size_t)k * s.fstride);
+    s.touched = A.get<int32_t>((size_t)k * B.n);
+    s.lists = A.get<int32_t>((size_t)k * 3 * B.n);
+    if (!s.key || !s.flags || !s.touched || !s.lists) return CHL_ERR_OOM;
+    HIPCHK(hipMemsetAsync(s.key, 0xFF, (size_t)k * B.n * kb, st));
+    HIPCHK(hipMemsetAsync(s.flags, 0, (size_t)k * s.fstride * 4, st));
+    return 0;
+}
+
+void free_slots(Arena& A, Slots& s) {
+    A.drop(s.key);
+    A.drop(s.flags);
+    A.drop(s.touched);
+    A.drop(s.lists);
+    s = Slots{};
+}
+
+int grow_pool(Arena& A, Build& B, unsigned long long used, unsigned long long want, hipStream_t st) {
+    unsigned long long cap = std::max<unsigned long long>(want, 2 * B.pool.cap);
+    Pool np = B.pool;
+    np.cap = cap;
+    np.v = A.get<int32_t>(cap);
+    np.hub = A.get<int32_t>(cap);
+    np.dist = A.get<int32_t>(cap);
+    if (!np.v || !np.hub || !np.dist) return CHL_ERR_OOM;
+    if (used) {
+        HIPCHK(hipMemcpyAsync(np.v, B.pool.v, used * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(np.hub, B.pool.hub, used * 4, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(np.dist, B.pool.dist, used * 4, hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    A.drop(B.pool.v);
+    A.drop(B.pool.hub);
+    A.drop(B.pool.dist);
+    B.pool = np;
+    return 0;
+}
+
+TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int32_t* roots,
+                  int32_t nroots) {
+    TreeParams p{};
+    p.g = B.g;
+    p.s = s;
+    p.pool = B.pool;
+    p.delta = delta;
+    p.early_term = early;
+    p.next_root = B.ctl32 + 0;
+    p.stop = B.ctl32 + 1;
+    p.nfailed = B.ctl32 + 2;
+    p.err = B.ctl32 + 3;
+    p.failed = B.failed;
+    p.far2 = B.far2;
+    p.nroots = nroots;
+    p.roots = roots;
+    p.stats = B.stats;
+    return p;
+}
+
+// Run the batched kernel over roots (NULL = all, in rank order) until every
+// root has emitted, growing the pool when it fills up.
+int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
+                const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches) {
+    std::vector<int32_t> pending;
+    const int32_t* dev_roots = nullptr;
+    if (roots_host) {
+        HIPCHK(hipMemcpyAsync(B.roots, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, st));
+        dev_roots = B.roots;
+    }
+    for (;;) {
+        HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
+        HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
+        TreeParams p = params(B, s, delta, early, dev_roots, nroots);
+        if (launch_tree_batched(p, B.key_bits, wg, st)) return CHL_ERR_HIP;
+        (*launches)++;
+        int32_t c32[4];
+        unsigned long long c64[2];
+        HIPCHK(hipMemcpyAsync(c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
+        if (!(c32[3] & ERR_BIT_POOL)) break;
+        // pool full: keep what fitted, then resume with the failed roots and
+        // the roots the queue had not handed out yet
+        unsigned long long used = std::min(c64[0], c64[1]);
+        int32_t nf = c32[2];
+        std::vector<int32_t> failed(nf);
+        if (nf) HIPCHK(hipMemcpy(failed.data(), B.failed, (size_t)nf * 4, hipMemcpyDeviceToHost));
+        int32_t next = std::min(c32[0], nroots);
+        std::vector<int32_t> rest;
+        rest.reserve(nf + (nroots - next));
+        rest.insert(rest.end(), failed.begin(), failed.end());
+        if (roots_host) {
+            rest.insert(rest.end(), roots_host + next, roots_host + nroots);
+        } else {
+            for (int32_t r = next; r < nroots; r++) rest.push_back(r);
+        }
+        // estimate the final size from the labels per root seen so far
+        int32_t done = std::max<int32_t>(1, next - nf);
+        unsigned long long est = used + (unsigned long long)((double)used / done * (double)rest.size() * 1.1) + 1024;
+        if (int r = grow_pool(A, B, used, est, st)) return r;
+        int32_t errclr = c32[3] & ~ERR_BIT_POOL;
+        HIPCHK(hipMemcpyAsync(B.ctl64, &used, 8, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(B.ctl32 + 3, &errclr, 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        pending.swap(rest);
+        nroots = (int32_t)pending.size();
+        roots_host = pending.data();
+        HIPCHK(hipMemcpyAsync(B.roots, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        dev_roots = B.roots;
+        if (nroots == 0) break;
+    }
+    return 0;
+}
+
+int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early, hipStream_t st,
+              int* launches) {
+    int grid = plain_grid_size(B.key_bits, wg);
+    if (grid <= 0) return CHL_ERR_HIP;
+    grid = std::min(grid, std::max(1, (B.n + wg - 1) / wg) * 4);
+    const int32_t CH = 1024;
+    std::vector<int32_t> todo;
+    for (int32_t r0 = 0; r0 < B.n; r0 += CH) {
+        todo.clear();
+        for (int32_t r = r0; r < std::min(B.n, r0 + CH); r++) todo.push_back(r);
+        while (!todo.empty()) {
+            HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));
+            HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));
+            for (int32_t r : todo) {
+                TreeParams p = params(B, s, delta, early, nullptr, 0);
+                if (launch_tree_plain(p, B.key_bits, wg, grid, r, B.gstate, st)) return CHL_ERR_HIP;
+                (*launches)++;
+            }
+            int32_t c32[4];
+            unsigned long long c64[2];
+            HIPCHK(hipMemcpyAsync(c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (!(c32[3] & ERR_BIT_POOL)) break;
+            // the pool filled up: keep what fitted, grow, redo the roots that failed
+            unsigned long long used = std::min(c64[0], c64[1]);
+            int32_t nf = c32[2];
+            std::vector<int32_t> failed(nf);
+            if (nf) HIPCHK(hipMemcpy(failed.data(), B.failed, (size_t)nf * 4, hipMemcpyDeviceToHost));
+            unsigned long long est = 2 * used + (unsigned long long)B.n * (unsigned long long)nf;
+            if (int r = grow_pool(A, B, used, std::min<unsigned long long>(est, used + (unsigned long long)B.n * 64), st)) return r;
+            int32_t errclr = c32[3] & ~ERR_BIT_POOL;
+            HIPCHK(hipMemcpyAsync(B.ctl64, &used, 8, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(B.ctl32 + 3, &errclr, 4, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::sort(failed.begin(), failed.end());
+            todo.swap(failed);
+        }
+    }
+    return 0;
+}
+
+uint64_t graph_signature(const chl_graph* g, hipStream_t st) {
+    // a few row offsets and arcs sampled at fixed positions
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+    mix((uint64_t)g->n);
+    mix((uint64_t)g->n_arcs);
+    for (int i = 0; i < 16; i++) {
+        int64_t v = (int64_t)g->n * i / 16, r = 0;
+        int64_t e = g->n_arcs ? g->n_arcs * i / 16 : 0;
+        int32_t c = 0, w = 0;
+        (void)hipMemcpyAsync(&r, g->row_ptr + v, 8, hipMemcpyDeviceToHost, st);
+        if (g->n_arcs) {
+            (void)hipMemcpyAsync(&c, g->col + e, 4, hipMemcpyDeviceToHost, st);
+            (void)hipMemcpyAsync(&w, g->w + e, 4, hipMemcpyDeviceToHost, st);
+        }
+        (void)hipStreamSynchronize(st);
+        mix((uint64_t)r);
+        mix((uint64_t)(uint32_t)c << 32 | (uint32_t)w);
+    }
+    return h;
+}
+
+}  // namespace
+
+static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
+                          const chl_allocator* alloc_in, void* stream, chl_labels** out);
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* chl_error_string(int code) {
+    switch (code) {
+        case CHL_OK: return "ok";
+        case CHL_ERR_INVALID_ARG: return "invalid argument";
+        case CHL_ERR_OOM: return "out of device memory";
+        case CHL_ERR_HIP: return "HIP runtime error";
+        case CHL_ERR_DIST_OVERFLOW: return "a label distance does not fit in int32";
+        case CHL_ERR_NO_DEVICE: return "no gfx950 device";
+        case CHL_ERR_BUSY: return "request rejected: over budget or queue full";
+        default: return "unknown error";
+    }
+}
+
+void chl_build_opts_default(chl_build_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->mode = CHL_MODE_BATCHED;
+    o->early_term = 1;
+    o->stats = 1;
+    o->autotune = 1;
+}
+
+int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
+              const chl_allocator* alloc, void* stream, chl_labels** out) {
+    try {
+        return chl_build_impl(g, order, opts, alloc, stream, out);
+    } catch (...) {
+        return CHL_ERR_OOM;
+    }
+}
+
+int chl_labels_info(const chl_labels* h, int32_t* n, int64_t* total) {
+    if (!h) return CHL_ERR_INVALID_ARG;
+    if (n) *n = h->n;
+    if (total) *total = h->total;
+    return CHL_OK;
+}
+
+int chl_labels_export(const chl_labels* h, int64_t* offsets, int32_t* hub_pos, int32_t* dist,
+                      int to_host, void* stream) {
+    if (!h) return CHL_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipMemcpyKind k = to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (offsets) HIPCHK(hipMemcpyAsync(offsets, h->offsets, (size_t)(h->n + 1) * 8, k, st));
+    if (hub_pos && h->total) HIPCHK(hipMemcpyAsync(hub_pos, h->hub_pos, (size_t)h->total * 4, k, st));
+    if (dist && h->total) HIPCHK(hipMemcpyAsync(dist, h->dist, (size_t)h->total * 4, k, st));
+    if (to_host) HIPCHK(hipStreamSynchronize(st));
+    return CHL_OK;
+}
+
+int chl_labels_hub_vertex(const chl_labels* h, int32_t* hub_vertex, int to_host, void* stream) {
+    if (!h || !hub_vertex) return CHL_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(hub_vertex, h->order, (size_t)h->n * 4,
+                          to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+    if (to_host) HIPCHK(hipStreamSynchronize(st));
+    return CHL_OK;
+}
+
+int chl_query(const chl_labels* hc, const int32_t* pairs, int64_t q, int64_t* out, void* stream) {
+    if (!hc || q < 0 || (q > 0 && (!pairs || !out))) return CHL_ERR_INVALID_ARG;
+    if (q == 0) return CHL_OK;
+    chl_labels* h = const_cast<chl_labels*>(hc);
+    hipStream_t st = (hipStream_t)stream;
+    // the error word is per handle: concurrent queries on one handle serialise here
+    std::lock_guard<std::mutex> lk(h->qmu);
+    HIPCHK(hipMemsetAsync(h->qerr, 0, 4, st));
+    double avg = h->n ? (double)h->total / h->n : 1.0;
+    if (launch_query(h->n, h->offsets, h->hub_pos, h->dist, pairs, q, out, h->qerr, avg, st))
+        return CHL_ERR_HIP;
+    int32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, h->qerr, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return e ? CHL_ERR_INVALID_ARG : CHL_OK;
+}
+
+int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root, int to_host, void* stream) {
+    if (!h) return CHL_ERR_INVALID_ARG;
+    if (per_root && !h->per_root) return CHL_ERR_INVALID_ARG;
+    if (totals) *totals = h->st;
+    if (per_root) {
+        hipStream_t st = (hipStream_t)stream;
+        HIPCHK(hipMemcpyAsync(per_root, h->per_root, (size_t)h->n * 32,
+                              to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
+        if (to_host) HIPCHK(hipStreamSynchronize(st));
+    }
+    return CHL_OK;
+}
+
+void chl_labels_free(chl_labels* h) {
+    if (!h) return;
+    auto f = [&](void* p) { if (p) h->alloc.free(p, h->alloc.ctx); };
+    f(h->offsets);
+    f(h->hub_pos);
+    f(h->dist);
+    f(h->order);
+    f(h->per_root);
+    f(h->qerr);
+    delete h;
+}
+
+}  // extern "C"
+
+// ====================================================================== build
+static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_opts& o,
+                       hipStream_t st, int& k, int& wg, int64_t& delta, double& tune_ms);
+
+static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
+                          const chl_allocator* alloc_in, void* stream, chl_labels** out) {
+    if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
+    if (g->n < 1 || g->n > 0x7FFFFFFE || g->n_arcs < 0 || g->n_arcs > 0xFFFFFFFFll) return CHL_ERR_INVALID_ARG;
+    if (!g->row_ptr || (g->n_arcs > 0 && (!g->col || !g->w))) return CHL_ERR_INVALID_ARG;
+    chl_build_opts o;
+    chl_build_opts_default(&o);
+    if (opts_in) o = *opts_in;
+    if (o.mode != CHL_MODE_BATCHED && o.mode != CHL_MODE_PLAIN) return CHL_ERR_INVALID_ARG;
+    if (o.wg_size != 0 && o.wg_size != 256 && o.wg_size != 512 && o.wg_size != 1024) return CHL_ERR_INVALID_ARG;
+    if (o.mode == CHL_MODE_PLAIN && o.wg_size == 1024) return CHL_ERR_INVALID_ARG;
+    if (o.roots_in_flight < 0 || o.delta < 0) return CHL_ERR_INVALID_ARG;
+    if (int r = check_device()) return r;
+    chl_allocator al = alloc_in ? *alloc_in : kDefaultAlloc;
+    if (!al.alloc || !al.free) return CHL_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    Arena A(al);
+    Build B;
+    B.n = g->n;
+    B.m = g->n_arcs;
+    const int32_t n = g->n;
+    chl_stats S{};
+    S.n = n;
+
+    // ---- validation and renumbering
+    Timer tprep(st);
+    B.ctl32 = A.get<int32_t>(16);
+    B.ctl64 = A.get<unsigned long long>(4);
+    int32_t* pos = A.get<int32_t>(n);
+    int32_t* cnt = A.get<int32_t>(n);
+    int64_t* rrow = A.get<int64_t>((size_t)n + 1);
+    int64_t* rdeg = A.get<int64_t>(n);
+    uint64_t* rarc = A.get<uint64_t>((size_t)std::max<int64_t>(1, B.m));
+    void* scan_tmp = A.get<uint8_t>(scan_temp_bytes(std::max<int64_t>(n, 1)));
+    int32_t* hub_order = A.get<int32_t>(n);
+    if (A.oom) return CHL_ERR_OOM;
+    HIPCHK(hipMemsetAsync(B.ctl32, 0, 64, st));
+    HIPCHK(hipMemsetAsync(B.ctl64, 0, 32, st));
+    HIPCHK(hipMemsetAsync(cnt, 0, (size_t)n * 4, st));
+    int32_t* err = B.ctl32 + 3;
+    int32_t* maxw = B.ctl32 + 4;
+    if (launch_validate(n, B.m, g->row_ptr, g->col, g->w, order, pos, cnt, err, maxw, st)) return CHL_ERR_HIP;
+    int32_t hv[2];
+    HIPCHK(hipMemcpyAsync(hv, err, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hv[0]) return CHL_ERR_INVALID_ARG;
+    B.maxw = std::max(1, hv[1]);
+    if (launch_rank_degrees(n, g->row_ptr, order, rdeg, st)) return CHL_ERR_HIP;
+    if (launch_scan_i64(rdeg, rrow, n, scan_tmp, st)) return CHL_ERR_HIP;
+    if (launch_renumber(n, B.m, g->row_ptr, g->col, g->w, order, pos, rrow, rarc, st)) return CHL_ERR_HIP;
+    if (launch_segsort_u64(rarc, rrow, n, B.m, nullptr, st)) return CHL_ERR_HIP;
+    if (launch_check_symmetric(n, rrow, rarc, err, st)) return CHL_ERR_HIP;
+    HIPCHK(hipMemcpyAsync(hub_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(hv, err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (hv[0]) return CHL_ERR_INVALID_ARG;
+    A.drop(rdeg);
+    A.drop(cnt);
+    S.prep_ms = tprep.stop();
+    B.g = RGraph{n, B.m, rrow, rarc};
+    // 32-bit keys are exact when no simple path can reach 2^31 - 1
+    B.key_bits = ((double)(n - 1) * (double)B.maxw <= 2147483646.0) ? 32 : 64;
+    S.key_bits = B.key_bits;
+
+    B.failed = A.get<int32_t>(n);
+    B.roots = A.get<int32_t>(n);
+    B.far2 = A.get<int32_t>(n);
+    B.gstate = (int32_t*)A.get<int64_t>(plain_gstate_words() + 8);
+    if (o.stats) B.stats = A.get<int64_t>((size_t)n * 4);
+    // initial pool: 16 labels per vertex, grown on demand
+    B.pool.cap = (unsigned long long)n * 16 + 4096;
+    B.pool.v = A.get<int32_t>(B.pool.cap);
+    B.pool.hub = A.get<int32_t>(B.pool.cap);
+    B.pool.dist = A.get<int32_t>(B.pool.cap);
+    B.pool.cursor = B.ctl64 + 0;
+    B.pool.fail_base = B.ctl64 + 1;
+    if (A.oom) return CHL_ERR_OOM;
+    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * 32, st));
+
+    // ---- parameters
+    int k = 0, wg = 0;
+    int64_t delta = 0;
+    double tune_ms = 0;
+    if (int r = pick_params(A, B, g, o, st, k, wg, delta, tune_ms)) return r;
+    S.tune_ms = tune_ms;
+    S.roots_in_flight = k;
+    S.wg_size = wg;
+    S.delta = delta;
+
+    // ---- trees
+    Slots s{};
+    if (int r = alloc_slots(A, B, o.mode == CHL_MODE_PLAIN ? 1 : k, s, st)) return r;
+    HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+    int launches = 0;
+    Timer ttree(st);
+    int r = o.mode == CHL_MODE_PLAIN ? run_plain(A, B, s, wg, delta, o.early_term, st, &launches)
+                                     : run_batched(A, B, s, wg, delta, o.early_term, nullptr, n, st, &launches);
+    if (r) return r;
+    S.tree_ms = ttree.stop();
+    S.launches = launches;
+    free_slots(A, s);
+    int32_t c32[4];
+    unsigned long long used = 0;
+    HIPCHK(hipMemcpyAsync(c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(&used, B.ctl64, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c32[3] & ERR_BIT_OVERFLOW) return CHL_ERR_DIST_OVERFLOW;
+    if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
+
+    // ---- assembly
+    Timer tasm(st);
+    chl_labels* L = new chl_labels();
+    L->n = n;
+    L->total = (int64_t)used;
+    L->alloc = al;
+    Arena keep(al);  // buffers handed to the handle
+    int32_t* count = A.get<int32_t>(n);
+    int32_t* fill = A.get<int32_t>(n);
+    uint64_t* tmp = A.get<uint64_t>(std::max<unsigned long long>(used, 1));
+    L->offsets = keep.get<int64_t>((size_t)n + 1);
+    L->hub_pos = keep.get<int32_t>(std::max<unsigned long long>(used, 1));
+    L->dist = keep.get<int32_t>(std::max<unsigned long long>(used, 1));
+    L->order = hub_order;
+    L->qerr = keep.get<int32_t>(4);
+    if (A.oom || keep.oom) { delete L; return CHL_ERR_OOM; }
+    if (launch_assemble(n, order, B.pool, used, count, L->offsets, fill, tmp, L->hub_pos, L->dist, scan_tmp,
+                        nullptr, st)) {
+        delete L;
+        return CHL_ERR_HIP;
+    }
+    S.assemble_ms = tasm.stop();
+    // totals of the per-root statistics
+    S.labels = (int64_t)used;
+    if (B.stats) {
+        std::vector<int64_t> pr((size_t)n * 4);
+        if (hipMemcpy(pr.data(), B.stats, (size_t)n * 32, hipMemcpyDeviceToHost) != hipSuccess) { delete L; return CHL_ERR_HIP; }
+        for (int32_t i = 0; i < n; i++) {
+            S.settled += pr[4 * i];
+            S.arcs += pr[4 * i + 1];
+            S.early_trees += pr[4 * i + 3];
+        }
+        L->per_root = B.stats;
+        A.release(B.stats);
+    }
+    A.release(hub_order);
+    keep.ptrs.clear();   // now owned by the handle
+    L->st = S;
+    *out = L;
+    return CHL_OK;
+}
+
+// ---------------------------------------------------------------- tuner
+static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_opts& o, hipStream_t st,
+                       int& k, int& wg, int64_t& delta, double& tune_ms) {
+    const int32_t n = B.n;
+    const double wmean = 0.5 * (1.0 + B.maxw);
+    size_t freeb = 0, totalb = 0;
+    (void)hipMemGetInfo(&freeb, &totalb);
+    size_t budget = freeb / 4;
+    int kmax = (int)std::max<size_t>(1, std::min<size_t>(4096, budget / std::max<size_t>(1, slot_bytes(n, B.key_bits))));
+    k = o.roots_in_flight ? std::min(o.roots_in_flight, kmax) : std::min(kmax, 1024);
+    wg = o.wg_size ? o.wg_size : 256;
+    delta = o.delta ? o.delta : std::max<int64_t>(1, (int64_t)(wmean));
+    if (o.mode == CHL_MODE_PLAIN) {
+        if (!o.wg_size) wg = 256;
+        if (!o.delta) delta = std::max<int64_t>(1, (int64_t)(4 * wmean));
+        return 0;
+    }
+    bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta);
+    if (!need) return 0;
+    TuneKey key{n, B.m, B.maxw, o.mode, graph_signature(g, st)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            if (!o.roots_in_flight) k = std::min(it->second.k, kmax);
+            if (!o.wg_size) wg = it->second.wg;
+            if (!o.delta) delta = it->second.delta;
+            return 0;
+        }
+    }
+    // probe: the first roots (largest trees) and a rank-stratified sample
+    std::vector<int32_t> probe;
+    int32_t head = std::min<int32_t>(n, 256);
+    for (int32_t r = 0; r < head; r++) probe.push_back(r);
+    int32_t strata = std::min<int32_t>(n - head, 768);
+    for (int32_t i = 0; i < strata; i++) probe.push_back(head + (int32_t)((int64_t)(n - head) * i / strata));
+    std::vector<int> ks, wgs;
+    std::vector<int64_t> ds;
+    if (o.roots_in_flight) ks = {k}; else for (int kk : {128, 256, 512, 1024, 2048}) if (kk <= kmax) ks.push_back(kk);
+    if (ks.empty()) ks = {kmax};
+    if (o.wg_size) wgs = {wg}; else wgs = {256, 512, 1024};
+    if (o.delta) ds = {delta};
+    else for (double f : {0.25, 0.5, 1.0, 2.0, 4.0, 8.0}) ds.push_back(std::max<int64_t>(1, (int64_t)(f * wmean)));
+    std::sort(ds.begin(), ds.end());
+    ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
+    auto t0 = std::chrono::steady_clock::now();
+    double best = 1e30;
+    TuneVal bv{k, wg, delta};
+    int launches = 0;
+    Slots s{};
+    int kcur = 0;
+    // stage 1: wg and delta at a middle k; stage 2: k at the best wg / delta
+    int kmid = ks[ks.size() / 2];
+    auto trial = [&](int kk, int w, int64_t d) -> int {
+        if (kk != kcur) {
+            free_slots(A, s);
+            if (int r = alloc_slots(A, B, kk, s, st)) return r;
+            kcur = kk;
+        }
+        HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+        Timer t(st);
+        if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st, &launches)) return r;
+        double ms = t.stop();
+        if (ms < best) { best = ms; bv = TuneVal{kk, w, d}; }
+        return 0;
+    };
+    for (int w : wgs)
+        for (int64_t d : ds)
+            if (int r = trial(kmid, w, d)) return r;
+    for (int kk : ks)
+        if (kk != kmid)
+            if (int r = trial(kk, bv.wg, bv.delta)) return r;
+    free_slots(A, s);
+    HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * 32, st));
+    HIPCHK(hipStreamSynchronize(st));
+    tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    k = bv.k;
+    wg = bv.wg;
+    delta = bv.delta;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = bv;
+    return 0;
+}

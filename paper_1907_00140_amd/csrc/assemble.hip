@@ -1,0 +1,76 @@
+// Label assembly: from the pool written by the trees (one entry per label,
+// in the order the trees finished) to one list per vertex, sorted by hub
+// rank position, most important hub first (the sort step of Algorithm 2;
+// the merge query of Section 5 needs it). Count labels per vertex (input
+// id), exclusive scan into offsets, scatter (hub << 32 | dist) words into
+// their vertex's segment, sort every segment, split into hub_pos / dist.
+// Hubs inside one L_v are distinct, so the sorted order is unique whatever
+// order the trees finished in.
+#include "internal.h"
+
+namespace chl {
+
+namespace {
+
+__global__ void k_zero32(int32_t* a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = 0;
+}
+
+__global__ void k_count(const int32_t* __restrict__ pv, uint64_t total, const int32_t* __restrict__ order,
+                        int32_t* __restrict__ count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&count[order[pv[i]]], 1);
+}
+
+__global__ void k_scatter(const int32_t* __restrict__ pv, const int32_t* __restrict__ ph,
+                          const int32_t* __restrict__ pd, uint64_t total, const int32_t* __restrict__ order,
+                          const int64_t* __restrict__ offsets, int32_t* __restrict__ fill,
+                          uint64_t* __restrict__ tmp) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int32_t v = order[pv[i]];
+        int64_t p = offsets[v] + atomicAdd(&fill[v], 1);
+        tmp[p] = ((uint64_t)(uint32_t)ph[i] << 32) | (uint32_t)pd[i];
+    }
+}
+
+__global__ void k_split(const uint64_t* __restrict__ tmp, uint64_t total, int32_t* __restrict__ hub,
+                        int32_t* __restrict__ dist) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t x = tmp[i];
+        hub[i] = (int32_t)(x >> 32);
+        dist[i] = (int32_t)(uint32_t)x;
+    }
+}
+
+int g(uint64_t work) {
+    uint64_t b = (work + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (int)b;
+}
+
+}  // namespace
+
+int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t total,
+                    int32_t* count, int64_t* offsets, int32_t* fill, uint64_t* tmp,
+                    int32_t* hub_pos, int32_t* dist, void* scan_temp, void* sort_temp,
+                    hipStream_t st) {
+    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, count, (int64_t)n);
+    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, fill, (int64_t)n);
+    if (total > 0)
+        hipLaunchKernelGGL(k_count, dim3(g(total)), dim3(256), 0, st, pool.v, total, order, count);
+    if (launch_scan_i32_to_i64(count, offsets, n, scan_temp, st)) return -1;
+    if (total > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(g(total)), dim3(256), 0, st, pool.v, pool.hub, pool.dist, total,
+                           order, offsets, fill, tmp);
+        if (launch_segsort_u64(tmp, offsets, n, (int64_t)total, sort_temp, st)) return -1;
+        hipLaunchKernelGGL(k_split, dim3(g(total)), dim3(256), 0, st, tmp, total, hub_pos, dist);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace chl

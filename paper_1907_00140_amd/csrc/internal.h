@@ -1,0 +1,137 @@
+// Internal declarations of the CHL library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+
+#include "../../include/chl.h"
+
+namespace chl {
+
+// ---------------------------------------------------------------- keys
+// A tree's per-vertex state is one packed key: (distance << 1) | clean, where
+// clean = 1 means that no vertex of any shortest root-v path found so far
+// outranks the root. An atomic minimum on the key keeps the shorter distance,
+// and on equal distance prefers clean = 0, which is the OR of "outranked"
+// over all equal-distance predecessors (the equal-distance ancestor update of
+// Algorithm 3, Section 4.2). All ones = not reached.
+template <typename K> struct KeyTraits;
+template <> struct KeyTraits<uint32_t> { static constexpr uint32_t INF = 0xFFFFFFFFu; };
+template <> struct KeyTraits<uint64_t> { static constexpr uint64_t INF = ~0ull; };
+
+// error bits written by kernels
+enum : int32_t {
+    ERR_BIT_OVERFLOW = 1,     // a label distance >= 2^31 - 1
+    ERR_BIT_INVALID = 2,      // invalid input detected on the device
+    ERR_BIT_POOL = 4,         // label pool full (host grows it and resumes)
+};
+
+// Graph after rank renumbering: vertex id = rank position, so "u outranks
+// the root h" is u < h. arcs[e] = (neighbour << 32) | weight, each row sorted.
+struct RGraph {
+    int32_t n;
+    int64_t m;
+    const int64_t* row;
+    const uint64_t* arc;
+};
+
+// Label pool written by the tree phase: one entry per label, in the order
+// trees finish (structure of arrays).
+struct Pool {
+    int32_t* v;       // labelled vertex (rank position)
+    int32_t* hub;     // hub (rank position = root)
+    int32_t* dist;    // distance
+    unsigned long long cap;
+    unsigned long long* cursor;     // device counter of used entries
+    unsigned long long* fail_base;  // smallest reservation that did not fit
+};
+
+// Per-slot state of the trees in flight.
+struct Slots {
+    int32_t k;            // number of slots
+    int64_t stride;       // elements per slot in key / touched / list arrays
+    int64_t fstride;      // flag words per slot
+    void* key;            // K[k][stride], all INF between trees
+    uint32_t* flags;      // [k][fstride], 4 bits per vertex, all 0 between trees
+    int32_t* touched;     // [k][stride]
+    int32_t* lists;       // [k][3][stride]: two near lists, one far list
+};
+
+struct TreeParams {
+    RGraph g;
+    Slots s;
+    Pool pool;
+    int64_t delta;
+    int32_t early_term;
+    // root work queue (batched form)
+    int32_t* next_root;     // device counter into roots[] (or into [0, n))
+    int32_t nroots;
+    const int32_t* roots;   // NULL: root index = counter value
+    int32_t* stop;          // set when the pool is full
+    int32_t* failed;        // roots that could not emit (pool full)
+    int32_t* nfailed;
+    int32_t* far2;          // plain form: filtered far list, n entries
+    // outputs
+    int64_t* stats;         // [n][4] by root or NULL
+    int32_t* err;
+};
+
+// ---------------------------------------------------------------- launchers
+// prep.hip
+int launch_validate(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                    const int32_t* w, const int32_t* order, int32_t* pos, int32_t* cnt,
+                    int32_t* err, int32_t* maxw, hipStream_t st);
+int launch_renumber(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                    const int32_t* w, const int32_t* order, const int32_t* pos,
+                    int64_t* rrow, uint64_t* rarc, hipStream_t st);
+int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order, int64_t* rdeg,
+                        hipStream_t st);
+int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc,
+                           int32_t* err, hipStream_t st);
+
+// scan.hip: exclusive prefix sum of int64 in[n] into out[n+1] (out[n] = total)
+size_t scan_temp_bytes(int64_t n);
+int launch_scan_i64(const int64_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
+int launch_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, void* temp, hipStream_t st);
+
+// segsort.hip: sort every segment [off[i], off[i+1]) of keys ascending
+size_t segsort_temp_bytes(int64_t nseg);
+int launch_segsort_u64(uint64_t* keys, const int64_t* off, int64_t nseg, int64_t total,
+                       void* temp, hipStream_t st);
+
+// tree.hip
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, hipStream_t st);
+int launch_tree_plain(const TreeParams& p, int key_bits, int wg, int grid, int32_t root,
+                      int32_t* gstate, hipStream_t st);
+int plain_grid_size(int key_bits, int wg);
+size_t plain_gstate_words();
+
+// assemble.hip
+int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t total,
+                    int32_t* count, int64_t* offsets, int32_t* fill, uint64_t* tmp,
+                    int32_t* hub_pos, int32_t* dist, void* scan_temp, void* sort_temp,
+                    hipStream_t st);
+
+// query.hip
+int launch_query(int32_t n, const int64_t* offsets, const int32_t* hub_pos, const int32_t* dist,
+                 const int32_t* pairs, int64_t q, int64_t* out, int32_t* err, double avg_len,
+                 hipStream_t st);
+
+}  // namespace chl
+
+// Device-resident labeling behind the opaque handle of the C-ABI.
+struct chl_labels {
+    int32_t n = 0;
+    int64_t total = 0;
+    int64_t* offsets = nullptr;   // [n+1], by input id
+    int32_t* hub_pos = nullptr;   // [total]
+    int32_t* dist = nullptr;      // [total]
+    int32_t* order = nullptr;     // [n] = hub_vertex
+    int64_t* per_root = nullptr;  // [n][4] or null
+    int32_t* qerr = nullptr;      // query error word
+    chl_stats st{};
+    chl_allocator alloc{};
+    std::mutex qmu;
+};

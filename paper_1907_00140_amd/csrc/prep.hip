@@ -1,0 +1,154 @@
+// Input validation and rank renumbering of the CSR.
+//
+// After renumbering, vertex id = rank position (order[0] -> 0, the most
+// important vertex; the paper's tree of v is built n - R(v)-th, Section 4.1),
+// so "u outranks h" is the integer comparison u < h, a root's hub id is its
+// index, and high-rank hubs are contiguous. Each renumbered row is sorted by
+// (neighbour, weight) and stored as one 64-bit word per arc,
+// (neighbour << 32) | weight, so the tree kernels read an arc with a single
+// 8-byte load.
+#include "internal.h"
+
+namespace chl {
+
+namespace {
+
+__global__ void k_order(int32_t n, const int32_t* __restrict__ order, int32_t* __restrict__ pos,
+                        int32_t* __restrict__ cnt, int32_t* err) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int32_t o = order[i];
+        if (o < 0 || o >= n) { atomicOr(err, ERR_BIT_INVALID); continue; }
+        atomicAdd(&cnt[o], 1);
+        pos[o] = (int32_t)i;
+    }
+}
+
+__global__ void k_rows(int32_t n, int64_t m, const int64_t* __restrict__ row,
+                       const int32_t* __restrict__ cnt, int32_t* err) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n;
+         v += (int64_t)gridDim.x * blockDim.x) {
+        bool bad = false;
+        if (v == 0) bad |= row[0] != 0;
+        if (v == n) bad |= row[n] != m;
+        if (v < n) bad |= row[v + 1] < row[v] || cnt[v] != 1;
+        if (bad) atomicOr(err, ERR_BIT_INVALID);
+    }
+}
+
+__global__ void k_arcs(int32_t n, int64_t m, const int32_t* __restrict__ col,
+                       const int32_t* __restrict__ w, int32_t* err, int32_t* maxw) {
+    int32_t mx = 0;
+    bool bad = false;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c = col[e], x = w[e];
+        bad |= c < 0 || c >= n || x < 1;
+        mx = max(mx, x);
+    }
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
+    if ((threadIdx.x & 63) == 0) atomicMax(maxw, mx);
+    if (bad) atomicOr(err, ERR_BIT_INVALID);
+}
+
+__global__ void k_rdeg(int32_t n, const int64_t* __restrict__ row, const int32_t* __restrict__ order,
+                       int64_t* __restrict__ rdeg) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v = order[p];
+        rdeg[p] = row[v + 1] - row[v];
+    }
+}
+
+// one wave per renumbered row
+__global__ void k_copy(int32_t n, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                       const int32_t* __restrict__ w, const int32_t* __restrict__ order,
+                       const int32_t* __restrict__ pos, const int64_t* __restrict__ rrow,
+                       uint64_t* __restrict__ rarc) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t p = wave; p < n; p += nwaves) {
+        int32_t v = order[p];
+        int64_t b = row[v], e = row[v + 1], o = rrow[p];
+        for (int64_t i = b + lane; i < e; i += 64)
+            rarc[o + (i - b)] = ((uint64_t)(uint32_t)pos[col[i]] << 32) | (uint32_t)w[i];
+    }
+}
+
+__device__ __forceinline__ int64_t lower(const uint64_t* a, int64_t lo, int64_t hi, uint64_t k) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// every arc (p, u, w) must be matched by as many (u, p, w) as there are
+// (p, u, w): rows are sorted, so both counts are run lengths found by binary
+// search. One wave per row.
+__global__ void k_sym(int32_t n, const int64_t* __restrict__ rrow, const uint64_t* __restrict__ rarc,
+                      int32_t* err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    bool bad = false;
+    for (int64_t p = wave; p < n; p += nwaves) {
+        int64_t b = rrow[p], e = rrow[p + 1];
+        for (int64_t i = b + lane; i < e; i += 64) {
+            uint64_t k = rarc[i];
+            if (i > b && rarc[i - 1] == k) continue;          // first of its run only
+            int64_t c1 = lower(rarc, i, e, k + 1) - i;
+            uint32_t u = (uint32_t)(k >> 32);
+            uint64_t kr = ((uint64_t)(uint32_t)p << 32) | (uint32_t)k;
+            int64_t ub = rrow[u], ue = rrow[u + 1];
+            int64_t l = lower(rarc, ub, ue, kr);
+            int64_t c2 = lower(rarc, l, ue, kr + 1) - l;
+            bad |= c1 != c2;
+        }
+    }
+    if (bad) atomicOr(err, ERR_BIT_INVALID);
+}
+
+int grid_for(int64_t work, int block) {
+    int64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+}  // namespace
+
+int launch_validate(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                    const int32_t* w, const int32_t* order, int32_t* pos, int32_t* cnt,
+                    int32_t* err, int32_t* maxw, hipStream_t st) {
+    hipLaunchKernelGGL(k_order, dim3(grid_for(n, 256)), dim3(256), 0, st, n, order, pos, cnt, err);
+    hipLaunchKernelGGL(k_rows, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, st, n, m, row_ptr, cnt, err);
+    if (m > 0)
+        hipLaunchKernelGGL(k_arcs, dim3(grid_for(m, 256)), dim3(256), 0, st, n, m, col, w, err, maxw);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_renumber(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                    const int32_t* w, const int32_t* order, const int32_t* pos,
+                    int64_t* rrow, uint64_t* rarc, hipStream_t st) {
+    // rrow is first filled with degrees (in rank order) by the caller's scan
+    (void)m;
+    hipLaunchKernelGGL(k_copy, dim3(grid_for((int64_t)n * 64, 256)), dim3(256), 0, st, n, row_ptr, col,
+                       w, order, pos, rrow, rarc);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order, int64_t* rdeg,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_rdeg, dim3(grid_for(n, 256)), dim3(256), 0, st, n, row_ptr, order, rdeg);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc, int32_t* err,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_sym, dim3(grid_for((int64_t)n * 64, 256)), dim3(256), 0, st, n, rrow, rarc, err);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace chl

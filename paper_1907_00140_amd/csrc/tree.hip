@@ -1,0 +1,602 @@
+// PLaNT trees on gfx950 (Section 4.2, Algorithm 3).
+//
+// One tree per root h computes exact distances d(h, v) and whether some
+// vertex of some shortest h-v path outranks h. v receives the label
+// (h, d(h, v)) exactly when no such vertex exists. Vertices are renumbered by
+// rank position, so "u outranks h" is u < h.
+//
+// Frontier: Dijkstra's priority queue is replaced by delta-stepping with a
+// near list (tentative distance below the current bucket bound T) and a far
+// list (everything else). Near vertices are relaxed in rounds until the
+// bucket is a fixpoint; then the far list is filtered, the bound moves to the
+// bucket of the smallest pending distance, and the next bucket starts.
+// Relaxation is an atomic minimum on the packed key (distance << 1 | clean):
+// the candidate of arc (v, u, w) is ((d_v + w) << 1) | (clean_v & (u > h)),
+// so a key that drops only in the clean bit is also an improvement, and on
+// equal distance the outranked flag wins (OR over equal-distance
+// predecessors: the equal-distance ancestor update of Algorithm 3).
+//
+// Early termination (Section 4.2): at a bucket boundary every vertex with a
+// distance below the bound is final. If no pending vertex (far list) is
+// clean, no clean vertex remains to be found: along any shortest path to a
+// clean vertex, the first vertex that is not final would be pending with its
+// final, clean key. The tree stops there; every clean key is then final.
+//
+// Dedup of the lists uses 4 bits per vertex in a flag word array: bit 0/1 =
+// "in near list 0/1" (the two near lists alternate between rounds), bit 2 =
+// "in far list". A vertex improved during a round is pushed to the next near
+// list unless its bit for that list is set, so every improvement made during
+// a round is relaxed in the next round, with no ordering needed between the
+// key update and the flag update. Lists therefore never hold a vertex twice
+// and fit in n entries.
+//
+// Batched form: a persistent kernel, one workgroup per tree; each workgroup
+// owns a slot of per-tree state and pops roots from a rank-ordered work queue
+// (the paper's atomic task counter, Section 3.1). Plain form: the whole grid
+// grows one tree per cooperative launch.
+#include <hip/hip_cooperative_groups.h>
+
+#include "internal.h"
+
+namespace cg = cooperative_groups;
+
+namespace chl {
+
+namespace {
+
+constexpr uint32_t FAR_BIT = 4u;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Append for every lane with pred set: one atomic per wave on *counter.
+// Returns the slot index for lanes with pred, undefined otherwise.
+template <typename C>
+__device__ __forceinline__ int64_t wave_append(bool pred, C* counter) {
+    uint64_t m = __ballot(pred);
+    if (m == 0) return -1;
+    int leader = __ffsll((unsigned long long)m) - 1;
+    int64_t base = 0;
+    if ((int)__lane_id() == leader) base = (int64_t)atomicAdd(counter, (C)__popcll(m));
+    base = __shfl(base, leader);
+    return base + lanes_below(m);
+}
+
+template <int SCOPE, typename T>
+__device__ __forceinline__ T ld(T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, SCOPE); }
+template <int SCOPE, typename T>
+__device__ __forceinline__ void st(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, SCOPE); }
+template <int SCOPE, typename T>
+__device__ __forceinline__ T amin(T* p, T v) { return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, SCOPE); }
+template <int SCOPE>
+__device__ __forceinline__ uint32_t aor(uint32_t* p, uint32_t v) { return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, SCOPE); }
+template <int SCOPE>
+__device__ __forceinline__ uint32_t aand(uint32_t* p, uint32_t v) { return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, SCOPE); }
+
+__device__ __forceinline__ uint32_t fshift(int32_t v) { return (uint32_t)(v & 7) * 4u; }
+
+// Block-wide exclusive scan of uint32 (WG threads). wsum: WG/64 entries of LDS.
+template <int WG>
+__device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* wsum, uint32_t& total) {
+    constexpr int NW = WG / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t y = __shfl_up(v, d);
+        if (lane >= d) v += y;
+    }
+    if (lane == 63) wsum[w] = v;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t s = lane < NW ? wsum[lane] : 0u;
+#pragma unroll
+        for (int d = 1; d < NW; d <<= 1) {
+            uint32_t y = __shfl_up(s, d);
+            if (lane >= d) s += y;
+        }
+        if (lane < NW) wsum[lane] = s;
+    }
+    __syncthreads();
+    total = wsum[NW - 1];
+    uint32_t ex = (w ? wsum[w - 1] : 0u) + v - x;
+    return ex;
+}
+
+template <int WG, typename T, typename F>
+__device__ __forceinline__ T block_reduce(T x, T* red, T ident, F op) {
+    constexpr int NW = WG / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x = op(x, __shfl_xor(x, d));
+    if (lane == 0) red[w] = x;
+    __syncthreads();
+    T r = ident;
+#pragma unroll
+    for (int i = 0; i < NW; i++) r = op(r, red[i]);
+    __syncthreads();
+    return r;
+}
+
+template <typename K>
+__device__ __forceinline__ K pack(uint64_t d, uint32_t clean) { return (K)((d << 1) | clean); }
+
+// LDS of the block-level frontier expansion.
+template <typename K, int WG>
+struct Expand {
+    int64_t beg[WG];
+    K key[WG];
+    uint32_t off[WG];
+    uint32_t wsum[WG / 64];
+};
+
+// Relax every arc of the vertices cur[base .. base+nv) (nv <= WG), balanced
+// over the block by arc index. Improved vertices go to the touched list (the
+// first time they are reached), to the next near list (new distance below
+// T) or to the far list, through wave-aggregated appends on the counters.
+template <typename K, int WG, int SCOPE, typename C>
+__device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* flags,
+                                            const int32_t* cur, int32_t base, int32_t nv,
+                                            uint32_t curbit, uint32_t nextbit, int32_t h,
+                                            int64_t T, int32_t* touched, int32_t* next,
+                                            int32_t* far, C* cnt_touched, C* cnt_next,
+                                            C* cnt_far, Expand<K, WG>& X, uint64_t& arcs) {
+    const int tid = threadIdx.x;
+    uint32_t deg = 0;
+    if (tid < nv) {
+        int32_t v = cur[base + tid];
+        aand<SCOPE>(&flags[v >> 3], ~(curbit << fshift(v)));
+        K kv = ld<SCOPE>(&key[v]);
+        int64_t b = g.row[v];
+        deg = (uint32_t)(g.row[v + 1] - b);
+        X.beg[tid] = b;
+        X.key[tid] = kv;
+    }
+    uint32_t total;
+    uint32_t ex = block_scan<WG>(deg, X.wsum, total);
+    X.off[tid] = ex;
+    __syncthreads();
+    arcs += total;
+    for (uint32_t e = tid; e < total; e += WG) {
+        int lo = 0, hi = nv - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (X.off[mid] <= e) lo = mid; else hi = mid - 1;
+        }
+        uint64_t a = g.arc[X.beg[lo] + (e - X.off[lo])];
+        int32_t u = (int32_t)(a >> 32);
+        uint32_t w = (uint32_t)a;
+        K kv = X.key[lo];
+        uint64_t nd = (uint64_t)(kv >> 1) + w;
+        K nk = pack<K>(nd, (uint32_t)(kv & 1) & (uint32_t)(u > h));
+        K old = amin<SCOPE>(&key[u], nk);
+        bool imp = nk < old;
+        bool first = imp && old == KeyTraits<K>::INF;
+        bool tonear = imp && (int64_t)nd < T;
+        bool pnear = false, pfar = false;
+        if (imp) {
+            uint32_t bit = (tonear ? nextbit : FAR_BIT) << fshift(u);
+            uint32_t o = aor<SCOPE>(&flags[u >> 3], bit);
+            bool fresh = (o & bit) == 0;
+            pnear = fresh && tonear;
+            pfar = fresh && !tonear;
+        }
+        int64_t p = wave_append(first, cnt_touched);
+        if (first) touched[p] = u;
+        p = wave_append(pnear, cnt_next);
+        if (pnear) next[p] = u;
+        p = wave_append(pfar, cnt_far);
+        if (pfar) far[p] = u;
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- batched
+template <typename K, int WG>
+struct BatchedLds {
+    Expand<K, WG> X;
+    unsigned long long red64[WG / 64];
+    int32_t red32[WG / 64];
+    int32_t ncur, cnt_next, cnt_far, cnt_touched, nkeep, nclean;
+    int32_t root;
+    unsigned long long minpend;
+    long long pool_base;
+};
+
+template <typename K, int WG>
+__global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
+    constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
+    __shared__ BatchedLds<K, WG> S;
+    const int tid = threadIdx.x;
+    const int32_t n = p.g.n;
+    const int64_t slot = blockIdx.x;
+    K* key = (K*)p.s.key + slot * p.s.stride;
+    uint32_t* flags = p.s.flags + slot * p.s.fstride;
+    int32_t* touched = p.s.touched + slot * p.s.stride;
+    int32_t* lists = p.s.lists + slot * 3 * p.s.stride;
+    int32_t* far = lists + 2 * p.s.stride;
+    const int64_t delta = p.delta;
+
+    for (;;) {
+        if (tid == 0) {
+            int32_t r = -1;
+            if (__hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                int32_t c = atomicAdd(p.next_root, 1);
+                if (c < p.nroots) r = p.roots ? p.roots[c] : c;
+            }
+            S.root = r;
+        }
+        __syncthreads();
+        const int32_t h = S.root;
+        if (h < 0) break;
+
+        // ---- init: root key (0, clean) in near list 0
+        if (tid == 0) {
+            st<SC>(&key[h], pack<K>(0, 1));
+            touched[0] = h;
+            lists[0] = h;
+            aor<SC>(&flags[h >> 3], 1u << fshift(h));
+            S.ncur = 1; S.cnt_next = 0; S.cnt_far = 0; S.cnt_touched = 1;
+        }
+        __syncthreads();
+        int64_t T = delta;
+        int it = 0;
+        uint64_t arcs = 0, settled = 0;
+        int32_t nfar = 0;
+        bool early = false;
+        for (;;) {
+            // ---- rounds inside the bucket until no near vertex is left
+            for (;;) {
+                const int32_t ncur = S.ncur;
+                const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
+                int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
+                int32_t* next = lists + (int64_t)((it + 1) & 1) * p.s.stride;
+                settled += ncur;
+                for (int32_t base = 0; base < ncur; base += WG)
+                    relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
+                                           nextbit, h, T, touched, next, far, &S.cnt_touched,
+                                           &S.cnt_next, &S.cnt_far, S.X, arcs);
+                __syncthreads();
+                it++;
+                if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
+                __syncthreads();
+                if (S.ncur == 0) break;
+            }
+            // ---- bucket done: drop settled far entries, find the smallest
+            //      pending distance and whether any pending vertex is clean
+            nfar = S.cnt_far;
+            if (tid == 0) { S.nkeep = 0; S.nclean = 0; S.minpend = ~0ull; }
+            __syncthreads();
+            unsigned long long mymin = ~0ull;
+            int32_t myclean = 0;
+            for (int32_t base = 0; base < nfar; base += WG) {
+                const int32_t i = base + tid;
+                bool keep = false;
+                int32_t v = 0;
+                K kv = 0;
+                if (i < nfar) {
+                    v = far[i];
+                    aand<SC>(&flags[v >> 3], ~(FAR_BIT << fshift(v)));
+                    kv = ld<SC>(&key[v]);
+                    keep = (int64_t)(kv >> 1) >= T;
+                }
+                __syncthreads();                         // chunk read before compaction writes
+                int64_t q = wave_append(keep, &S.nkeep);
+                if (keep) {
+                    far[q] = v;
+                    mymin = min(mymin, (unsigned long long)(kv >> 1));
+                    myclean += (int32_t)(kv & 1);
+                }
+                __syncthreads();
+            }
+            unsigned long long mn = block_reduce<WG>(mymin, S.red64, ~0ull,
+                [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
+            int32_t ncl = block_reduce<WG>(myclean, S.red32, 0, [](int32_t a, int32_t b) { return a + b; });
+            nfar = S.nkeep;
+            if (nfar == 0 || (p.early_term && ncl == 0)) { early = nfar > 0; break; }
+            // ---- next bucket: the one holding the smallest pending distance
+            T = ((int64_t)mn / delta + 1) * delta;
+            int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
+            const uint32_t curbit = 1u << (it & 1);
+            if (tid == 0) { S.ncur = 0; S.cnt_far = 0; }
+            __syncthreads();
+            for (int32_t base = 0; base < nfar; base += WG) {
+                const int32_t i = base + tid;
+                int32_t v = 0;
+                bool tonear = false, tofar = false;
+                if (i < nfar) {
+                    v = far[i];
+                    K kv = ld<SC>(&key[v]);
+                    tonear = (int64_t)(kv >> 1) < T;
+                    tofar = !tonear;
+                }
+                __syncthreads();
+                int64_t q = wave_append(tonear, &S.ncur);
+                if (tonear) { cur[q] = v; aor<SC>(&flags[v >> 3], curbit << fshift(v)); }
+                q = wave_append(tofar, &S.cnt_far);
+                if (tofar) { far[q] = v; aor<SC>(&flags[v >> 3], FAR_BIT << fshift(v)); }
+                __syncthreads();
+            }
+        }
+        // far entries left behind have had their far bit cleared by the filter
+
+        // ---- emit labels of clean vertices, reset the slot
+        const int32_t nt = S.cnt_touched;
+        int32_t mycnt = 0;
+        for (int32_t i = tid; i < nt; i += WG) mycnt += (int32_t)(ld<SC>(&key[touched[i]]) & 1);
+        const int32_t nl = block_reduce<WG>(mycnt, S.red32, 0, [](int32_t a, int32_t b) { return a + b; });
+        if (tid == 0) {
+            unsigned long long b = atomicAdd(p.pool.cursor, (unsigned long long)nl);
+            if (b + (unsigned long long)nl > p.pool.cap) {
+                S.pool_base = -1;
+                atomicOr(p.err, ERR_BIT_POOL);
+                atomicExch(p.stop, 1);
+                atomicMin(p.pool.fail_base, b);
+                p.failed[atomicAdd(p.nfailed, 1)] = h;
+            } else {
+                S.pool_base = (long long)b;
+            }
+            S.nkeep = 0;
+        }
+        __syncthreads();
+        const long long pb = S.pool_base;
+        bool ovf = false;
+        for (int32_t base = 0; base < nt; base += WG) {
+            const int32_t i = base + tid;
+            bool lab = false;
+            int32_t v = 0;
+            uint64_t d = 0;
+            if (i < nt) {
+                v = touched[i];
+                K kv = ld<SC>(&key[v]);
+                lab = (kv & 1) != 0;
+                d = (uint64_t)(kv >> 1);
+                st<SC>(&key[v], KeyTraits<K>::INF);
+            }
+            int64_t q = wave_append(lab, &S.nkeep);
+            if (lab && pb >= 0) {
+                ovf |= d > 0x7FFFFFFEull;
+                p.pool.v[pb + q] = v;
+                p.pool.hub[pb + q] = h;
+                p.pool.dist[pb + q] = (int32_t)d;
+            }
+        }
+        if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
+        if (p.stats && tid == 0) {
+            // every thread of the block accumulated the same settled / arc counts
+            int64_t* s = p.stats + (int64_t)h * 4;
+            s[0] = (int64_t)settled; s[1] = (int64_t)arcs; s[2] = nl; s[3] = early ? 1 : 0;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- plain
+// Device-wide tree: every workgroup of a cooperative grid works on the same
+// root. Global state words (int64):
+enum {
+    G_CNT0 = 0, G_CNT1, G_CNT2,   // near list counts, rotating by round % 3
+    G_FAR, G_FAR2, G_TOUCHED,     // far list, filtered far list, touched list
+    G_MIN, G_CLEAN, G_T, G_DONE, G_EARLY,
+    G_SETTLED, G_ARCS, G_NLAB, G_BASE, G_FILL,
+    G_WORDS
+};
+
+template <typename K, int WG>
+struct PlainLds {
+    Expand<K, WG> X;
+    unsigned long long red64[WG / 64];
+};
+
+template <typename K, int WG>
+__global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long long* gs) {
+    constexpr int SC = __HIP_MEMORY_SCOPE_AGENT;
+    __shared__ PlainLds<K, WG> S;
+    cg::grid_group grid = cg::this_grid();
+    const int tid = threadIdx.x;
+    const int64_t gtid = (int64_t)blockIdx.x * WG + tid;
+    const int64_t gthreads = (int64_t)gridDim.x * WG;
+    K* key = (K*)p.s.key;
+    uint32_t* flags = p.s.flags;
+    int32_t* touched = p.s.touched;
+    int32_t* lists = p.s.lists;            // near0, near1, far
+    int32_t* far = lists + 2 * p.s.stride;
+    int32_t* far2 = p.far2;                // filtered far list (n entries)
+    const int64_t delta = p.delta;
+
+    if (gtid == 0) {
+        for (int i = 0; i < G_WORDS; i++) gs[i] = 0;
+        gs[G_MIN] = 0x7FFFFFFFFFFFFFFFll;
+        st<SC>(&key[h], pack<K>(0, 1));
+        touched[0] = h;
+        lists[0] = h;
+        aor<SC>(&flags[h >> 3], 1u << fshift(h));
+        gs[G_CNT0] = 1;
+        gs[G_TOUCHED] = 1;
+        gs[G_T] = delta;
+        __threadfence();
+    }
+    grid.sync();
+    int it = 0;
+    uint64_t arcs = 0;
+    for (;;) {
+        // ---- one round over the near list
+        const int64_t T = gs[G_T];
+        const int32_t ncur = (int32_t)gs[G_CNT0 + it % 3];
+        const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
+        int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
+        int32_t* next = lists + (int64_t)((it + 1) & 1) * p.s.stride;
+        if (ncur > 0) {
+            for (int32_t base = blockIdx.x * WG; base < ncur; base += gridDim.x * WG)
+                relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
+                                       nextbit, h, T, touched, next, far,
+                                       (unsigned long long*)&gs[G_TOUCHED],
+                                       (unsigned long long*)&gs[G_CNT0 + (it + 1) % 3],
+                                       (unsigned long long*)&gs[G_FAR], S.X, arcs);
+            if (gtid == 0) { gs[G_CNT0 + (it + 2) % 3] = 0; gs[G_SETTLED] += ncur; }
+            __threadfence();
+            grid.sync();
+            it++;
+            continue;
+        }
+        // ---- bucket done: filter far into far2 (drop settled entries)
+        const int32_t nfar = (int32_t)gs[G_FAR];
+        unsigned long long mymin = ~0ull, myclean = 0;
+        for (int64_t i = gtid; i < nfar; i += gthreads) {
+            int32_t v = far[i];
+            aand<SC>(&flags[v >> 3], ~(FAR_BIT << fshift(v)));
+            K kv = ld<SC>(&key[v]);
+            bool keep = (int64_t)(kv >> 1) >= T;
+            if (keep) {
+                mymin = min(mymin, (unsigned long long)(kv >> 1));
+                myclean += (unsigned long long)(kv & 1);
+            }
+            int64_t q = wave_append(keep, (unsigned long long*)&gs[G_FAR2]);
+            if (keep) far2[q] = v;
+        }
+        mymin = block_reduce<WG>(mymin, S.red64, ~0ull,
+            [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
+        myclean = block_reduce<WG>(myclean, S.red64, 0ull,
+            [](unsigned long long a, unsigned long long b) { return a + b; });
+        if (tid == 0) {
+            if (mymin != ~0ull) atomicMin((unsigned long long*)&gs[G_MIN], mymin);
+            atomicAdd((unsigned long long*)&gs[G_CLEAN], myclean);
+        }
+        __threadfence();
+        grid.sync();
+        const int32_t nkeep = (int32_t)gs[G_FAR2];
+        const bool done = nkeep == 0 || (p.early_term && gs[G_CLEAN] == 0);
+        const int64_t Tn = ((int64_t)gs[G_MIN] / delta + 1) * delta;
+        grid.sync();                              // everyone has read the filter results
+        if (done) {
+            if (gtid == 0) gs[G_EARLY] = nkeep > 0;
+            break;
+        }
+        if (gtid == 0) {
+            gs[G_FAR] = 0; gs[G_FAR2] = 0; gs[G_CLEAN] = 0; gs[G_MIN] = 0x7FFFFFFFFFFFFFFFll;
+            gs[G_T] = Tn;
+        }
+        // far2 -> near (current list of the next round) or back to far
+        int32_t* ncurl = lists + (int64_t)(it & 1) * p.s.stride;
+        const uint32_t nb = 1u << (it & 1);
+        grid.sync();
+        for (int64_t i = gtid; i < nkeep; i += gthreads) {
+            int32_t v = far2[i];
+            K kv = ld<SC>(&key[v]);
+            bool tonear = (int64_t)(kv >> 1) < Tn;
+            int64_t q = wave_append(tonear, (unsigned long long*)&gs[G_CNT0 + it % 3]);
+            if (tonear) { ncurl[q] = v; aor<SC>(&flags[v >> 3], nb << fshift(v)); }
+            q = wave_append(!tonear, (unsigned long long*)&gs[G_FAR]);
+            if (!tonear) { far[q] = v; aor<SC>(&flags[v >> 3], FAR_BIT << fshift(v)); }
+        }
+        __threadfence();
+        grid.sync();
+    }
+    // ---- emit
+    const int64_t nt = gs[G_TOUCHED];
+    unsigned long long mycnt = 0;
+    for (int64_t i = gtid; i < nt; i += gthreads) mycnt += (unsigned long long)(ld<SC>(&key[touched[i]]) & 1);
+    mycnt = block_reduce<WG>(mycnt, S.red64, 0ull, [](unsigned long long a, unsigned long long b) { return a + b; });
+    if (tid == 0) atomicAdd((unsigned long long*)&gs[G_NLAB], mycnt);
+    if (tid == 0) atomicAdd((unsigned long long*)&gs[G_ARCS], (unsigned long long)arcs);
+    __threadfence();
+    grid.sync();
+    if (gtid == 0) {
+        unsigned long long nl = (unsigned long long)gs[G_NLAB];
+        unsigned long long b = atomicAdd(p.pool.cursor, nl);
+        if (b + nl > p.pool.cap) {
+            gs[G_BASE] = -1;
+            atomicOr(p.err, ERR_BIT_POOL);
+            atomicMin(p.pool.fail_base, b);
+            p.failed[atomicAdd(p.nfailed, 1)] = h;
+        } else {
+            gs[G_BASE] = (long long)b;
+        }
+        __threadfence();
+    }
+    grid.sync();
+    const long long pb = gs[G_BASE];
+    bool ovf = false;
+    for (int64_t i = gtid; i < nt; i += gthreads) {
+        int32_t v = touched[i];
+        K kv = ld<SC>(&key[v]);
+        bool lab = (kv & 1) != 0;
+        uint64_t d = (uint64_t)(kv >> 1);
+        st<SC>(&key[v], KeyTraits<K>::INF);
+        int64_t q = wave_append(lab, (unsigned long long*)&gs[G_FILL]);
+        if (lab && pb >= 0) {
+            ovf |= d > 0x7FFFFFFEull;
+            p.pool.v[pb + q] = v;
+            p.pool.hub[pb + q] = h;
+            p.pool.dist[pb + q] = (int32_t)d;
+        }
+    }
+    if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
+    if (p.stats && gtid == 0) {
+        // counters of this tree are complete after the last grid barrier
+        int64_t* s = p.stats + (int64_t)h * 4;
+        s[0] = gs[G_SETTLED]; s[1] = gs[G_ARCS]; s[2] = gs[G_NLAB]; s[3] = gs[G_EARLY];
+    }
+}
+
+template <typename K, int WG>
+int launch_batched_t(const TreeParams& p, hipStream_t st) {
+    hipLaunchKernelGGL((k_tree_batched<K, WG>), dim3(p.s.k), dim3(WG), 0, st, p);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int launch_plain_t(const TreeParams& p, int grid, int32_t root, int32_t* gstate, hipStream_t st) {
+    TreeParams pp = p;
+    long long* gs = (long long*)gstate;
+    void* args[] = {(void*)&pp, (void*)&root, (void*)&gs};
+    hipError_t e = hipLaunchCooperativeKernel((const void*)k_tree_plain<K, WG>, dim3(grid), dim3(WG),
+                                              args, 0, st);
+    return e == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int plain_grid_t() {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tree_plain<K, WG>, WG, 0) != hipSuccess) return 0;
+    return per * cus;
+}
+
+}  // namespace
+
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, hipStream_t st) {
+    if (key_bits == 32) {
+        if (wg == 256) return launch_batched_t<uint32_t, 256>(p, st);
+        if (wg == 512) return launch_batched_t<uint32_t, 512>(p, st);
+        if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, st);
+    } else {
+        if (wg == 256) return launch_batched_t<uint64_t, 256>(p, st);
+        if (wg == 512) return launch_batched_t<uint64_t, 512>(p, st);
+        if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, st);
+    }
+    return -1;
+}
+
+int launch_tree_plain(const TreeParams& p, int key_bits, int wg, int grid, int32_t root,
+                      int32_t* gstate, hipStream_t st) {
+    if (key_bits == 32) {
+        if (wg == 256) return launch_plain_t<uint32_t, 256>(p, grid, root, gstate, st);
+        if (wg == 512) return launch_plain_t<uint32_t, 512>(p, grid, root, gstate, st);
+    } else {
+        if (wg == 256) return launch_plain_t<uint64_t, 256>(p, grid, root, gstate, st);
+        if (wg == 512) return launch_plain_t<uint64_t, 512>(p, grid, root, gstate, st);
+    }
+    return -1;
+}
+
+int plain_grid_size(int key_bits, int wg) {
+    if (key_bits == 32) return wg == 256 ? plain_grid_t<uint32_t, 256>() : plain_grid_t<uint32_t, 512>();
+    return wg == 256 ? plain_grid_t<uint64_t, 256>() : plain_grid_t<uint64_t, 512>();
+}
+
+size_t plain_gstate_words() { return G_WORDS; }
+
+}  // namespace chl

@@ -1,0 +1,68 @@
+"""CPU-side checks of the C-ABI library: it loads, and it exports every
+function that include/chl.h declares. No device work is started here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "chl.h")
+LIB = os.path.join(ROOT, "paper_1907_00140_amd", "libchl.so")
+
+
+def declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b(chl_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_1907_00140_amd.build as b
+        b.build(verbose=False)
+    return ctypes.CDLL(LIB)
+
+
+def test_header_parses():
+    names = declared()
+    for must in ("chl_build", "chl_query", "chl_labels_export", "chl_labels_free",
+                 "chl_error_string", "chl_build_stats", "chl_server_create"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_error_strings(lib):
+    f = lib.chl_error_string
+    f.restype = ctypes.c_char_p
+    f.argtypes = [ctypes.c_int]
+    seen = set()
+    for code in range(0, -7, -1):
+        s = f(code)
+        assert s and s not in seen
+        seen.add(s)
+    assert f(-99) == b"unknown error"
+
+
+def test_binding_signatures_cover_header():
+    from paper_1907_00140_amd import chl
+    lib = chl.load()
+    for n in declared():
+        assert getattr(lib, n).argtypes is not None or n == "chl_error_string", n
+
+
+def test_product_does_not_reach_the_oracle():
+    """The product package never imports the CPU oracle."""
+    pkg = os.path.join(ROOT, "paper_1907_00140_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "chl_oracle" not in txt, f

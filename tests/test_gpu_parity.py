@@ -1,0 +1,198 @@
+"""HIP build and queries against the CPU oracle, bit-exact, through the C-ABI.
+
+Labels are unique for a graph and a ranking (the canonical labeling), so
+every comparison is an exact equality of offsets, hubs and distances.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+import pins
+from gpu_util import assert_same_labels, gpu_labels, per_root_from_export
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a device"
+    from paper_1907_00140_amd import chl
+    chl.load()
+
+
+@pytest.mark.parametrize("name", ["fig1_example.txt", "reading1_counterexample.txt"])
+@pytest.mark.parametrize("mode", ["batched", "plain"])
+def test_golden_ties(name, mode):
+    _say("golden", name, mode)
+    n, order, edges, want = pins.load_golden(name)
+    row, col, w = pins.csr_from_edges(n, edges)
+    L, off, hub, dist = gpu_labels(row, col, w, order, mode=mode, delta=1, autotune=False)
+    ref = oracle.chl(row, col, w, order)
+    assert_same_labels(off, hub, dist, ref, name)
+    got = {v: list(zip(hub[off[v]:off[v + 1]].tolist(), dist[off[v]:off[v + 1]].tolist())) for v in range(n)}
+    assert got == want
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small(seed):
+    """Random multigraphs with few distinct weights (many ties), ragged sizes."""
+    g = np.random.default_rng(seed)
+    n = int(g.integers(2, 300))
+    m = int(g.integers(n // 2, 3 * n))
+    wmax = int(g.integers(1, 6))
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = pins.csr_from_edges(n, e)
+    order = gg.random_rank(n, seed) if seed % 2 else gg.degree_rank(row, seed)
+    _say("random_small", seed, n, m, wmax)
+    ref = oracle.chl(row, col, w, order)
+    for kw in (dict(mode="batched", delta=1 + seed % 4, roots_in_flight=1 + seed % 7, wg_size=256, autotune=False),
+               dict(mode="batched", delta=1000, wg_size=512, autotune=False),
+               dict(mode="plain", delta=2, autotune=False)):
+        L, off, hub, dist = gpu_labels(row, col, w, order, **kw)
+        assert_same_labels(off, hub, dist, ref, str(kw))
+
+
+def test_grid64_full():
+    """64x64 grid workload: full labeling, both forms, plus its 10^4 queries."""
+    c = gg.make_config("grid64")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    for kw in (dict(mode="batched"), dict(mode="batched", early_term=False, autotune=False),
+               dict(mode="plain", autotune=False)):
+        _say("grid64", kw)
+        L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], **kw)
+        assert_same_labels(off, hub, dist, ref, str(kw))
+    qref = oracle.query(ref, c["pairs"])
+    q = L.query(c["pairs"]).cpu().numpy()
+    assert np.array_equal(q, qref)
+
+
+@pytest.mark.parametrize("k,wg,delta", [(1, 256, 1), (3, 512, 7), (64, 1024, 50), (256, 256, 100),
+                                        (1024, 512, 400), (2048, 256, 10_000)])
+def test_parameter_invariance_rmat12(k, wg, delta):
+    """Every (roots in flight, workgroup size, bucket width) gives the same labels."""
+    c = gg.make_config("rmat12s9")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    _say("invariance", k, wg, delta)
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], mode="batched",
+                                   roots_in_flight=k, wg_size=wg, delta=delta, autotune=False)
+    assert_same_labels(off, hub, dist, ref)
+
+
+def test_repeatable_rmat14():
+    """Repeated builds give identical labels (no order-dependent races)."""
+    c = gg.make_config("rmat14s11")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    for i in range(3):
+        _say("repeat", i)
+        L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"])
+        assert_same_labels(off, hub, dist, ref)
+    q = L.query(c["pairs"]).cpu().numpy()
+    assert np.array_equal(q, oracle.query(ref, c["pairs"]))
+
+
+def test_rmat16_full():
+    """R-MAT scale 16 workload: full labeling bit-exact, and 10^6 queries."""
+    c = gg.make_config("rmat16")
+    _say("rmat16 oracle")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    _say("rmat16 gpu")
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"])
+    assert_same_labels(off, hub, dist, ref)
+    q = L.query(c["pairs"]).cpu().numpy()
+    assert np.array_equal(q, oracle.query(ref, c["pairs"]))
+    st = L.stats(per_root=True)
+    assert st["labels"] == ref.total
+    assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])   # labels per root
+
+
+def test_invalid_inputs():
+    from paper_1907_00140_amd import chl
+    row, col, w = pins.csr_from_edges(4, [(0, 1, 1), (1, 2, 2), (2, 3, 1)])
+    order = np.arange(4, dtype=np.int32)
+    bad = [
+        (row, col, w, np.array([0, 1, 1, 3], np.int32)),        # not a permutation
+        (row, col, w, np.array([0, 1, 2, 4], np.int32)),        # out of range
+        (row, col, np.where(w == 2, 0, w).astype(np.int32), order),   # zero weight
+        (row, col, np.where(w == 2, -3, w).astype(np.int32), order),  # negative weight
+        (row, np.where(col == 3, 7, col).astype(np.int32), w, order),  # neighbour out of range
+    ]
+    # asymmetric: change one direction's weight
+    w2 = w.copy()
+    w2[0] = 5
+    bad.append((row, col, w2, order))
+    r2 = row.copy()
+    r2[-1] += 1                                                  # row_ptr[n] != n_arcs
+    bad.append((r2, col, w, order))
+    for i, (r, c_, ww, o) in enumerate(bad):
+        _say("invalid", i)
+        with pytest.raises(chl.ChlError) as e:
+            chl.build(r, c_, ww, o)
+        assert e.value.code == -1
+    L = chl.build(row, col, w, order)
+    with pytest.raises(chl.ChlError):
+        L.query(np.array([[0, 4]], np.int32))
+    assert L.query(np.zeros((0, 2), np.int32)).numel() == 0
+
+
+def test_edge_cases():
+    """Single vertex, isolated vertices, self-loops and parallel arcs."""
+    from paper_1907_00140_amd import chl
+    # one vertex, no arcs
+    L = chl.build(np.array([0, 0], np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                  np.array([0], np.int32))
+    off, hub, dist = L.export("cpu")
+    assert off.tolist() == [0, 1] and hub.tolist() == [0] and dist.tolist() == [0]
+    assert L.query(np.array([[0, 0]], np.int32)).cpu().tolist() == [0]
+    # self-loops and parallel arcs, plus an isolated vertex
+    edges = [(0, 1, 5), (0, 1, 2), (1, 1, 3), (1, 2, 1), (2, 0, 9), (2, 0, 9)]
+    row, col, w = pins.csr_from_edges(4, edges)
+    order = np.array([2, 0, 3, 1], np.int32)
+    ref = oracle.chl(row, col, w, order)
+    L, off, hub, dist = gpu_labels(row, col, w, order, autotune=False, delta=1)
+    assert_same_labels(off, hub, dist, ref)
+    q = L.query(np.array([[0, 2], [3, 1], [3, 3], [1, 0]], np.int32)).cpu().tolist()
+    assert q == [3, -1, 0, 2]
+
+
+def test_distance_overflow():
+    """A label distance of 2^31 - 1 or more is an error; just below is fine."""
+    from paper_1907_00140_amd import chl
+    big = 2**30
+    row, col, w = pins.csr_from_edges(3, [(0, 1, big), (1, 2, big - 2)])
+    order = np.array([0, 1, 2], np.int32)
+    L, off, hub, dist = gpu_labels(row, col, w, order, autotune=False, delta=1 << 20)
+    assert dist.max() == 2 * big - 2
+    row, col, w = pins.csr_from_edges(3, [(0, 1, big), (1, 2, big - 1)])
+    with pytest.raises(chl.ChlError) as e:
+        chl.build(row, col, w, order, autotune=False, delta=1 << 20)
+    assert e.value.code == -4
+
+
+def test_grid_large_sampled():
+    """256x256 grid with diagonal shortcuts: per-root parity on the top roots
+    and a rank-stratified sample (roots are independent, Section 4.2)."""
+    c = gg.make_config("grid256x256_3")
+    n = c["n"]
+    roots = list(range(64)) + list(np.linspace(64, n - 1, 192).astype(int))
+    _say("grid256 gpu")
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"])
+    _say("grid256 oracle roots")
+    want, _ = oracle.roots(c["row_ptr"], c["col"], c["w"], c["order"], roots)
+    got = per_root_from_export(off, hub, dist, c["order"], roots)
+    for r, (v, d) in zip(roots, want):
+        gv, gd = got[int(r)]
+        assert np.array_equal(gv, v) and np.array_equal(gd, d), r
+    # every L_v strictly increasing in hub
+    seg_first = np.zeros(len(hub), bool)
+    seg_first[off[:-1][np.diff(off) > 0]] = True
+    assert (np.diff(hub.astype(np.int64))[~seg_first[1:]] > 0).all()
