@@ -1,0 +1,148 @@
+"""Benchmark of the PLaNT CHL build and distance queries on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: chl_build of
+the complete canonical labeling of the R-MAT scale-16 graph (validation, rank
+renumbering, the batched persistent tree kernel, label assembly) followed by
+chl_query on its 10^6 query pairs. Inputs (CSR, ranking, pairs) are resident
+in device memory before the timed region starts.
+
+value = build GTEPS = arcs scanned by the reference Dijkstra trees (counted
+by the CPU oracle with early termination) / build time / 1e9.
+
+Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = "rmat16"
+COUNTS = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_tree_batched_rmat16.json")
+TREE_SRC = os.path.join(ROOT, "paper_1907_00140_amd", "csrc", "tree.hip")
+
+
+def src_sha():
+    return hashlib.sha256(open(TREE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="also run a short open-loop serving measurement")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(every tree is independent; see the sharding design in the docs)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import graphgen as gg
+    from paper_1907_00140_amd import chl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    c = gg.make_config(WORKLOAD)
+    counts = json.load(open(COUNTS))[WORKLOAD]
+    A, S, Lc = counts["arcs"], counts["settled"], counts["labels"]
+    row = torch.from_numpy(c["row_ptr"]).to(dev)
+    col = torch.from_numpy(c["col"]).to(dev)
+    w = torch.from_numpy(c["w"]).to(dev)
+    order = torch.from_numpy(c["order"]).to(dev)
+    pairs = torch.from_numpy(c["pairs"]).to(dev)
+    q = pairs.shape[0]
+    qout = torch.empty(q, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        L = chl.build(row, col, w, order, stream=stream)
+        L.query(pairs, out=qout, stream=stream)
+        return L
+
+    for _ in range(args.warmup):
+        L = step()
+        assert L.info()[1] == Lc, "label count differs from the oracle's"
+        L.free()
+    torch.cuda.synchronize()
+    build_ms, query_ms, tree_ms, launches, stats = [], [], [], [], None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        tb = time.perf_counter()
+        L = chl.build(row, col, w, order, stream=stream)
+        torch.cuda.synchronize()
+        tq = time.perf_counter()
+        L.query(pairs, out=qout, stream=stream)
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        build_ms.append((tq - tb) * 1e3)
+        query_ms.append((te - tq) * 1e3)
+        stats = L.stats()
+        tree_ms.append(stats["tree_ms"])
+        launches.append(stats["launches"])
+        L.free()
+    torch.cuda.synchronize()
+    total_s = time.perf_counter() - t0
+    b_s = float(np.median(build_ms)) / 1e3
+    gteps = A / b_s / 1e9
+    qps = q / (float(np.median(query_ms)) / 1e3)
+
+    # roofline of the dominant kernel (batched tree kernel): algorithmic bytes
+    # 16 per scanned arc + 16 per settled vertex + 8 per label (oracle counts)
+    alg_bytes = 16 * A + 16 * S + 8 * Lc
+    per_launch_ms = float(np.median(tree_ms)) / max(1, int(np.median(launches)))
+    achieved = alg_bytes / max(1, int(np.median(launches))) / (per_launch_ms / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC):
+        tr = json.load(open(TRAFFIC))
+        if tr.get("tree_src_sha") == src_sha():
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+                "kernel": "k_tree_batched", "kernel_ms": round(per_launch_ms, 3),
+                "alg_bytes_per_launch": alg_bytes / max(1, int(np.median(launches)))}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(16, os.cpu_count() or 1)
+        tc = time.perf_counter()
+        lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], mode=oracle.MODE_PLANT, threads=threads)
+        ct = time.perf_counter() - tc
+        assert lab.total == Lc
+        cpu = {"value": round(A / ct / 1e9, 4), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+               "sample": "full R-MAT scale-16 labeling (all 65,536 roots), %.1f s" % ct}
+
+    out = {
+        "metric": "CHL build time (s) + GTEPS; PPSD queries/s with p50/p99 latency, 1 MI355X",
+        "value": round(gteps, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(total_s / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "R-MAT scale 16 (65,536 vertices, %d edges), int32 weights [1,1000], degree rank; "
+                               "full canonical labeling + 10^6 uniform queries" % c["m"],
+                   "mode": "batched", "roots_in_flight": stats["roots_in_flight"], "wg_size": stats["wg_size"],
+                   "delta": stats["delta"], "key_bits": stats["key_bits"]},
+        "build_s": round(b_s, 4), "queries_per_s": round(qps, 1), "labels": Lc,
+        "gpu_arcs": stats["arcs"], "oracle_arcs": A, "work_inflation": round(stats["arcs"] / A, 3),
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    if args.serve:
+        from paper_1907_00140_amd import serve
+        out["serve"] = serve.quick_latency(L=None, workload=c, qps=qps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -226,7 +226,7 @@ class Labels:
         ptr = None
         if per_root:
             n, _ = self.info()
-            pr = np.zeros((n, 4), np.int64)
+            pr = np.zeros((n, 6), np.int64)
             ptr = pr.ctypes.data
         _check(self.lib.chl_build_stats(self._h, C.byref(s), ptr, 1, _stream_ptr()), "chl_build_stats")
         d = {f: getattr(s, f) for f, _ in CStats._fields_}

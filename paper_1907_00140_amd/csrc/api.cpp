@@ -239,9 +239,9 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         } else {
             for (int32_t r = next; r < nroots; r++) rest.push_back(r);
         }
-        // estimate the final size from the labels per root seen so far
-        int32_t done = std::max<int32_t>(1, next - nf);
-        unsigned long long est = used + (unsigned long long)((double)used / done * (double)rest.size() * 1.1) + 1024;
+        // grow by doubling: label counts per root fall steeply with rank, so
+        // the roots seen so far do not predict the rest
+        unsigned long long est = used + 1024;
         if (int r = grow_pool(A, B, used, est, st)) return r;
         int32_t errclr = c32[3] & ~ERR_BIT_POOL;
         HIPCHK(hipMemcpyAsync(B.ctl64, &used, 8, hipMemcpyHostToDevice, st));
@@ -287,8 +287,7 @@ int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int ear
             int32_t nf = c32[2];
             std::vector<int32_t> failed(nf);
             if (nf) HIPCHK(hipMemcpy(failed.data(), B.failed, (size_t)nf * 4, hipMemcpyDeviceToHost));
-            unsigned long long est = 2 * used + (unsigned long long)B.n * (unsigned long long)nf;
-            if (int r = grow_pool(A, B, used, std::min<unsigned long long>(est, used + (unsigned long long)B.n * 64), st)) return r;
+            if (int r = grow_pool(A, B, used, used + 1024, st)) return r;
             int32_t errclr = c32[3] & ~ERR_BIT_POOL;
             HIPCHK(hipMemcpyAsync(B.ctl64, &used, 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(B.ctl32 + 3, &errclr, 4, hipMemcpyHostToDevice, st));
@@ -412,7 +411,7 @@ int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root, i
     if (totals) *totals = h->st;
     if (per_root) {
         hipStream_t st = (hipStream_t)stream;
-        HIPCHK(hipMemcpyAsync(per_root, h->per_root, (size_t)h->n * 32,
+        HIPCHK(hipMemcpyAsync(per_root, h->per_root, (size_t)h->n * STAT_COLS * 8,
                               to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, st));
         if (to_host) HIPCHK(hipStreamSynchronize(st));
     }
@@ -505,16 +504,16 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     B.roots = A.get<int32_t>(n);
     B.far2 = A.get<int32_t>(n);
     B.gstate = (int32_t*)A.get<int64_t>(plain_gstate_words() + 8);
-    if (o.stats) B.stats = A.get<int64_t>((size_t)n * 4);
+    if (o.stats) B.stats = A.get<int64_t>((size_t)n * STAT_COLS);
     // initial pool: 16 labels per vertex, grown on demand
-    B.pool.cap = (unsigned long long)n * 16 + 4096;
+    B.pool.cap = (unsigned long long)n * 64 + 4096;
     B.pool.v = A.get<int32_t>(B.pool.cap);
     B.pool.hub = A.get<int32_t>(B.pool.cap);
     B.pool.dist = A.get<int32_t>(B.pool.cap);
     B.pool.cursor = B.ctl64 + 0;
     B.pool.fail_base = B.ctl64 + 1;
     if (A.oom) return CHL_ERR_OOM;
-    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * 32, st));
+    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
 
     // ---- parameters
     int k = 0, wg = 0;
@@ -571,12 +570,12 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     // totals of the per-root statistics
     S.labels = (int64_t)used;
     if (B.stats) {
-        std::vector<int64_t> pr((size_t)n * 4);
-        if (hipMemcpy(pr.data(), B.stats, (size_t)n * 32, hipMemcpyDeviceToHost) != hipSuccess) { delete L; return CHL_ERR_HIP; }
+        std::vector<int64_t> pr((size_t)n * STAT_COLS);
+        if (hipMemcpy(pr.data(), B.stats, (size_t)n * STAT_COLS * 8, hipMemcpyDeviceToHost) != hipSuccess) { delete L; return CHL_ERR_HIP; }
         for (int32_t i = 0; i < n; i++) {
-            S.settled += pr[4 * i];
-            S.arcs += pr[4 * i + 1];
-            S.early_trees += pr[4 * i + 3];
+            S.settled += pr[STAT_COLS * i];
+            S.arcs += pr[STAT_COLS * i + 1];
+            S.early_trees += pr[STAT_COLS * i + 3];
         }
         L->per_root = B.stats;
         A.release(B.stats);
@@ -620,28 +619,21 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     // probe: the first roots (largest trees) and a rank-stratified sample
     std::vector<int32_t> probe;
-    int32_t head = std::min<int32_t>(n, 256);
+    int32_t head = std::min<int32_t>(n, 128);
     for (int32_t r = 0; r < head; r++) probe.push_back(r);
-    int32_t strata = std::min<int32_t>(n - head, 768);
+    int32_t strata = std::min<int32_t>(n - head, 384);
     for (int32_t i = 0; i < strata; i++) probe.push_back(head + (int32_t)((int64_t)(n - head) * i / strata));
-    std::vector<int> ks, wgs;
-    std::vector<int64_t> ds;
-    if (o.roots_in_flight) ks = {k}; else for (int kk : {128, 256, 512, 1024, 2048}) if (kk <= kmax) ks.push_back(kk);
-    if (ks.empty()) ks = {kmax};
-    if (o.wg_size) wgs = {wg}; else wgs = {256, 512, 1024};
-    if (o.delta) ds = {delta};
-    else for (double f : {0.25, 0.5, 1.0, 2.0, 4.0, 8.0}) ds.push_back(std::max<int64_t>(1, (int64_t)(f * wmean)));
-    std::sort(ds.begin(), ds.end());
-    ds.erase(std::unique(ds.begin(), ds.end()), ds.end());
     auto t0 = std::chrono::steady_clock::now();
     double best = 1e30;
     TuneVal bv{k, wg, delta};
     int launches = 0;
     Slots s{};
     int kcur = 0;
-    // stage 1: wg and delta at a middle k; stage 2: k at the best wg / delta
-    int kmid = ks[ks.size() / 2];
+    std::map<std::tuple<int, int, int64_t>, double> seen;
     auto trial = [&](int kk, int w, int64_t d) -> int {
+        kk = std::max(1, std::min(kk, kmax));
+        d = std::max<int64_t>(1, d);
+        if (seen.count({kk, w, d})) return 0;
         if (kk != kcur) {
             free_slots(A, s);
             if (int r = alloc_slots(A, B, kk, s, st)) return r;
@@ -651,18 +643,32 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         Timer t(st);
         if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st, &launches)) return r;
         double ms = t.stop();
+        seen[{kk, w, d}] = ms;
         if (ms < best) { best = ms; bv = TuneVal{kk, w, d}; }
         return 0;
     };
-    for (int w : wgs)
-        for (int64_t d : ds)
-            if (int r = trial(kmid, w, d)) return r;
-    for (int kk : ks)
-        if (kk != kmid)
+    // coordinate search: bucket width (coarse, then refined), workgroup
+    // size at a fixed thread count, then trees in flight
+    const int k0 = o.roots_in_flight ? k : std::min(kmax, 512);
+    const int w0 = o.wg_size ? wg : 512;
+    if (!o.delta) {
+        for (double f : {1.0 / 64, 1.0 / 16, 0.25, 1.0, 4.0})
+            if (int r = trial(k0, w0, (int64_t)(f * wmean))) return r;
+        int64_t d0 = bv.delta;
+        for (double f : {0.5, 2.0})
+            if (int r = trial(k0, w0, (int64_t)(f * d0))) return r;
+    }
+    if (!o.wg_size)
+        for (int w : {256, 1024})
+            if (int r = trial(o.roots_in_flight ? k : k0 * w0 / w, w, bv.delta)) return r;
+    if (!o.roots_in_flight) {
+        int kb = bv.k;
+        for (int kk : {kb / 2, kb * 2})
             if (int r = trial(kk, bv.wg, bv.delta)) return r;
+    }
     free_slots(A, s);
     HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
-    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * 32, st));
+    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
     HIPCHK(hipStreamSynchronize(st));
     tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     k = bv.k;

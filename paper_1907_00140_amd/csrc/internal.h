@@ -21,6 +21,10 @@ template <typename K> struct KeyTraits;
 template <> struct KeyTraits<uint32_t> { static constexpr uint32_t INF = 0xFFFFFFFFu; };
 template <> struct KeyTraits<uint64_t> { static constexpr uint64_t INF = ~0ull; };
 
+// per-root statistics columns: vertex relaxations, arcs relaxed, labels,
+// stopped early, relaxation rounds, device wall-clock ticks of the tree
+constexpr int STAT_COLS = 6;
+
 // error bits written by kernels
 enum : int32_t {
     ERR_BIT_OVERFLOW = 1,     // a label distance >= 2^31 - 1
@@ -74,7 +78,7 @@ struct TreeParams {
     int32_t* nfailed;
     int32_t* far2;          // plain form: filtered far list, n entries
     // outputs
-    int64_t* stats;         // [n][4] by root or NULL
+    int64_t* stats;         // [n][STAT_COLS] by root or NULL
     int32_t* err;
 };
 

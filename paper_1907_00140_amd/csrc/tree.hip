@@ -132,16 +132,23 @@ struct Expand {
 };
 
 // Relax every arc of the vertices cur[base .. base+nv) (nv <= WG), balanced
-// over the block by arc index. Improved vertices go to the touched list (the
-// first time they are reached), to the next near list (new distance below
-// T) or to the far list, through wave-aggregated appends on the counters.
+// over the block by arc index: thread t handles arcs t, t+WG, ... of the
+// chunk, RELAX_ILP of them at a time so that their loads are in flight
+// together. Improved vertices go to the touched list (the first time they
+// are reached), to the next near list (new distance below T) or to the far
+// list, through wave-aggregated appends on the counters. Every clean key
+// set here raises *umax (largest clean distance so far); clean far pushes
+// are counted in *cnt_far_clean.
+constexpr int RELAX_ILP = 4;
+
 template <typename K, int WG, int SCOPE, typename C>
 __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* flags,
                                             const int32_t* cur, int32_t base, int32_t nv,
                                             uint32_t curbit, uint32_t nextbit, int32_t h,
                                             int64_t T, int32_t* touched, int32_t* next,
                                             int32_t* far, C* cnt_touched, C* cnt_next,
-                                            C* cnt_far, Expand<K, WG>& X, uint64_t& arcs) {
+                                            C* cnt_far, C* cnt_far_clean, unsigned long long* umax,
+                                            Expand<K, WG>& X, uint64_t& arcs) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -158,37 +165,68 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
     X.off[tid] = ex;
     __syncthreads();
     arcs += total;
-    for (uint32_t e = tid; e < total; e += WG) {
-        int lo = 0, hi = nv - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (X.off[mid] <= e) lo = mid; else hi = mid - 1;
+    unsigned long long my_umax = 0;
+    bool my_umax_set = false;
+    for (uint32_t e0 = tid; e0 < total; e0 += WG * RELAX_ILP) {
+        int own[RELAX_ILP];
+        uint64_t a[RELAX_ILP];
+        K seen[RELAX_ILP];
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (X.off[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            own[j] = lo;
         }
-        uint64_t a = g.arc[X.beg[lo] + (e - X.off[lo])];
-        int32_t u = (int32_t)(a >> 32);
-        uint32_t w = (uint32_t)a;
-        K kv = X.key[lo];
-        uint64_t nd = (uint64_t)(kv >> 1) + w;
-        K nk = pack<K>(nd, (uint32_t)(kv & 1) & (uint32_t)(u > h));
-        K old = amin<SCOPE>(&key[u], nk);
-        bool imp = nk < old;
-        bool first = imp && old == KeyTraits<K>::INF;
-        bool tonear = imp && (int64_t)nd < T;
-        bool pnear = false, pfar = false;
-        if (imp) {
-            uint32_t bit = (tonear ? nextbit : FAR_BIT) << fshift(u);
-            uint32_t o = aor<SCOPE>(&flags[u >> 3], bit);
-            bool fresh = (o & bit) == 0;
-            pnear = fresh && tonear;
-            pfar = fresh && !tonear;
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            a[j] = e < total ? g.arc[X.beg[own[j]] + (e - X.off[own[j]])] : 0;
         }
-        int64_t p = wave_append(first, cnt_touched);
-        if (first) touched[p] = u;
-        p = wave_append(pnear, cnt_next);
-        if (pnear) next[p] = u;
-        p = wave_append(pfar, cnt_far);
-        if (pfar) far[p] = u;
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            seen[j] = e < total ? ld<SCOPE>(&key[(int32_t)(a[j] >> 32)]) : (K)0;
+        }
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            const bool valid = e < total;
+            const int32_t u = (int32_t)(a[j] >> 32);
+            const K kv = X.key[own[j]];
+            const uint64_t nd = (uint64_t)(kv >> 1) + (uint32_t)a[j];
+            const K nk = pack<K>(nd, (uint32_t)(kv & 1) & (uint32_t)(u > h));
+            // Keys only decrease, so a value read earlier is never below the
+            // current one: when the candidate is not below it, the atomic
+            // would fail and is skipped.
+            K old = seen[j];
+            if (valid && nk < seen[j]) old = amin<SCOPE>(&key[u], nk);
+            const bool imp = valid && nk < old;
+            const bool first = imp && old == KeyTraits<K>::INF;
+            const bool tonear = imp && (int64_t)nd < T;
+            bool pnear = false, pfar = false;
+            if (imp) {
+                if (nk & 1) { my_umax = my_umax > nd ? my_umax : nd; my_umax_set = true; }
+                uint32_t bit = (tonear ? nextbit : FAR_BIT) << fshift(u);
+                uint32_t o = aor<SCOPE>(&flags[u >> 3], bit);
+                bool fresh = (o & bit) == 0;
+                pnear = fresh && tonear;
+                pfar = fresh && !tonear;
+            }
+            int64_t q = wave_append(first, cnt_touched);
+            if (first) touched[q] = u;
+            q = wave_append(pnear, cnt_next);
+            if (pnear) next[q] = u;
+            q = wave_append(pfar, cnt_far);
+            if (pfar) far[q] = u;
+            const bool pfc = pfar && (nk & 1);
+            (void)wave_append(pfc, cnt_far_clean);
+        }
     }
+    if (my_umax_set) atomicMax(umax, my_umax);
     __syncthreads();
 }
 
@@ -198,18 +236,46 @@ struct BatchedLds {
     Expand<K, WG> X;
     unsigned long long red64[WG / 64];
     int32_t red32[WG / 64];
-    int32_t ncur, cnt_next, cnt_far, cnt_touched, nkeep, nclean;
+    int32_t ncur, cnt_next, cnt_far, cnt_touched, nkeep, far_clean;
     int32_t root;
-    unsigned long long minpend;
+    unsigned long long umax;
     long long pool_base;
 };
+
+// Early termination between rounds. Pending vertices are the current near
+// list and the far list. If none of them is clean, and no pending distance
+// can be at or below the largest clean distance ever set (umax), no later
+// relaxation can create or change a clean key: every vertex whose true key
+// is clean already has it (the first unfinished vertex on a shortest path to
+// it would be pending and clean), and every clean key is final. The pending
+// distances are bounded below by the smallest near key and by T (far
+// entries hold distances >= T; a far vertex whose key dropped below T has
+// been pushed to the near list as well). far_clean counts clean pushes to
+// the far list since the last filter, an upper bound of its clean entries.
+template <typename K, int WG, int SC>
+__device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, const int32_t* cur,
+                                         int32_t ncur, int64_t T) {
+    const int tid = threadIdx.x;
+    unsigned long long mn = ~0ull;
+    int32_t cl = 0;
+    for (int32_t i = tid; i < ncur; i += WG) {
+        K kv = ld<SC>(const_cast<K*>(&key[cur[i]]));
+        unsigned long long d = (unsigned long long)(kv >> 1);
+        mn = d < mn ? d : mn;
+        cl |= (int32_t)(kv & 1);
+    }
+    mn = block_reduce<WG>(mn, S.red64, ~0ull,
+        [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
+    cl = block_reduce<WG>(cl, S.red32, 0, [](int32_t a, int32_t b) { return a | b; });
+    unsigned long long lb = mn < (unsigned long long)T ? mn : (unsigned long long)T;
+    return cl == 0 && lb > S.umax;
+}
 
 template <typename K, int WG>
 __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
     __shared__ BatchedLds<K, WG> S;
     const int tid = threadIdx.x;
-    const int32_t n = p.g.n;
     const int64_t slot = blockIdx.x;
     K* key = (K*)p.s.key + slot * p.s.stride;
     uint32_t* flags = p.s.flags + slot * p.s.fstride;
@@ -238,35 +304,47 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             lists[0] = h;
             aor<SC>(&flags[h >> 3], 1u << fshift(h));
             S.ncur = 1; S.cnt_next = 0; S.cnt_far = 0; S.cnt_touched = 1;
+            S.far_clean = 0; S.umax = 0;
         }
         __syncthreads();
         int64_t T = delta;
         int it = 0;
         uint64_t arcs = 0, settled = 0;
-        int32_t nfar = 0;
+        const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
         bool early = false;
         for (;;) {
             // ---- rounds inside the bucket until no near vertex is left
+            bool stopped = false;
             for (;;) {
                 const int32_t ncur = S.ncur;
                 const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
                 int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
                 int32_t* next = lists + (int64_t)((it + 1) & 1) * p.s.stride;
+                if (p.early_term && S.far_clean == 0 && may_stop<K, WG, SC>(S, key, cur, ncur, T)) {
+                    // drop the pending entries: clear their list bits
+                    for (int32_t i = tid; i < ncur; i += WG) aand<SC>(&flags[cur[i] >> 3], ~(curbit << fshift(cur[i])));
+                    for (int32_t i = tid; i < S.cnt_far; i += WG) aand<SC>(&flags[far[i] >> 3], ~(FAR_BIT << fshift(far[i])));
+                    early = ncur > 0 || S.cnt_far > 0;
+                    stopped = true;
+                    __syncthreads();
+                    break;
+                }
                 settled += ncur;
                 for (int32_t base = 0; base < ncur; base += WG)
                     relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
-                                           &S.cnt_next, &S.cnt_far, S.X, arcs);
+                                           &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, S.X, arcs);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
                 __syncthreads();
                 if (S.ncur == 0) break;
             }
+            if (stopped) break;
             // ---- bucket done: drop settled far entries, find the smallest
             //      pending distance and whether any pending vertex is clean
-            nfar = S.cnt_far;
-            if (tid == 0) { S.nkeep = 0; S.nclean = 0; S.minpend = ~0ull; }
+            int32_t nfar = S.cnt_far;
+            if (tid == 0) { S.nkeep = 0; }
             __syncthreads();
             unsigned long long mymin = ~0ull;
             int32_t myclean = 0;
@@ -299,27 +377,29 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             T = ((int64_t)mn / delta + 1) * delta;
             int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
             const uint32_t curbit = 1u << (it & 1);
-            if (tid == 0) { S.ncur = 0; S.cnt_far = 0; }
+            if (tid == 0) { S.ncur = 0; S.cnt_far = 0; S.far_clean = 0; }
             __syncthreads();
             for (int32_t base = 0; base < nfar; base += WG) {
                 const int32_t i = base + tid;
                 int32_t v = 0;
-                bool tonear = false, tofar = false;
+                bool tonear = false, tofar = false, fclean = false;
                 if (i < nfar) {
                     v = far[i];
                     K kv = ld<SC>(&key[v]);
                     tonear = (int64_t)(kv >> 1) < T;
                     tofar = !tonear;
+                    fclean = tofar && (kv & 1);
                 }
                 __syncthreads();
                 int64_t q = wave_append(tonear, &S.ncur);
                 if (tonear) { cur[q] = v; aor<SC>(&flags[v >> 3], curbit << fshift(v)); }
                 q = wave_append(tofar, &S.cnt_far);
                 if (tofar) { far[q] = v; aor<SC>(&flags[v >> 3], FAR_BIT << fshift(v)); }
+                (void)wave_append(fclean, &S.far_clean);
                 __syncthreads();
             }
         }
-        // far entries left behind have had their far bit cleared by the filter
+        // far entries left behind have had their far bit cleared
 
         // ---- emit labels of clean vertices, reset the slot
         const int32_t nt = S.cnt_touched;
@@ -365,8 +445,9 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
         if (p.stats && tid == 0) {
             // every thread of the block accumulated the same settled / arc counts
-            int64_t* s = p.stats + (int64_t)h * 4;
+            int64_t* s = p.stats + (int64_t)h * STAT_COLS;
             s[0] = (int64_t)settled; s[1] = (int64_t)arcs; s[2] = nl; s[3] = early ? 1 : 0;
+            s[4] = it; s[5] = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
         }
         __syncthreads();
     }
@@ -379,7 +460,7 @@ enum {
     G_CNT0 = 0, G_CNT1, G_CNT2,   // near list counts, rotating by round % 3
     G_FAR, G_FAR2, G_TOUCHED,     // far list, filtered far list, touched list
     G_MIN, G_CLEAN, G_T, G_DONE, G_EARLY,
-    G_SETTLED, G_ARCS, G_NLAB, G_BASE, G_FILL,
+    G_SETTLED, G_ARCS, G_NLAB, G_BASE, G_FILL, G_FARCLEAN, G_UMAX,
     G_WORDS
 };
 
@@ -433,7 +514,9 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
                                        nextbit, h, T, touched, next, far,
                                        (unsigned long long*)&gs[G_TOUCHED],
                                        (unsigned long long*)&gs[G_CNT0 + (it + 1) % 3],
-                                       (unsigned long long*)&gs[G_FAR], S.X, arcs);
+                                       (unsigned long long*)&gs[G_FAR],
+                                       (unsigned long long*)&gs[G_FARCLEAN],
+                                       (unsigned long long*)&gs[G_UMAX], S.X, arcs);
             if (gtid == 0) { gs[G_CNT0 + (it + 2) % 3] = 0; gs[G_SETTLED] += ncur; }
             __threadfence();
             grid.sync();
@@ -535,8 +618,9 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
     if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
     if (p.stats && gtid == 0) {
         // counters of this tree are complete after the last grid barrier
-        int64_t* s = p.stats + (int64_t)h * 4;
+        int64_t* s = p.stats + (int64_t)h * STAT_COLS;
         s[0] = gs[G_SETTLED]; s[1] = gs[G_ARCS]; s[2] = gs[G_NLAB]; s[3] = gs[G_EARLY];
+        s[4] = it; s[5] = 0;
     }
 }
 
