@@ -226,3 +226,11 @@ def make_config(name):
 
 
 CONFIGS = ("grid64", "rmat16", "grid1024d", "rmat20")
+
+
+def poisson_arrivals(q, rate, seed, t0=0.0):
+    """Arrival times (seconds, non-decreasing) of an open-loop Poisson stream
+    of q requests at `rate` per second: cumulative sums of exponential gaps
+    drawn from PCG64(seed)."""
+    gaps = _rng(seed).exponential(1.0 / rate, size=q)
+    return t0 + np.cumsum(gaps)

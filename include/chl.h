@@ -106,7 +106,13 @@ typedef struct chl_build_opts {
     int32_t autotune;        /* 1: parameters left at 0 are chosen by timing a
                                 probe set of roots (cached per graph signature);
                                 0: they take fixed defaults */
-    int32_t reserved;
+    int32_t root_count;      /* 0: every root (the complete labeling). > 0: only
+                                the roots at rank positions root_begin +
+                                i * root_stride, i < root_count; the result then
+                                holds exactly the labels whose hub is one of
+                                them (trees are independent, Section 4.2) */
+    int32_t root_begin;
+    int32_t root_stride;     /* >= 1 when root_count > 0 */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */
@@ -217,6 +223,10 @@ int chl_server_submit_queries(chl_server* s, int32_t graph_id, const int32_t* pa
 int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int64_t* row_ptr,
                             const int32_t* col, const int32_t* w, const int32_t* order,
                             double t_arrival, int32_t* graph_id, double* lat, int32_t* status);
+
+/* Device-memory footprint (bytes) that admission charges for a build of a
+ * graph with n vertices and n_arcs arcs on this server. */
+size_t chl_server_build_footprint(const chl_server* s, int32_t n, int64_t n_arcs);
 
 /* Start the clock and the dispatch thread; returns immediately. */
 int chl_server_start(chl_server* s);

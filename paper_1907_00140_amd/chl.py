@@ -48,7 +48,8 @@ class CAllocator(C.Structure):
 class CBuildOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("roots_in_flight", C.c_int32), ("wg_size", C.c_int32),
                 ("delta", C.c_int64), ("early_term", C.c_int32), ("stats", C.c_int32),
-                ("autotune", C.c_int32), ("reserved", C.c_int32)]
+                ("autotune", C.c_int32), ("root_count", C.c_int32), ("root_begin", C.c_int32),
+                ("root_stride", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -93,6 +94,7 @@ def load(path=LIB_PATH):
             "chl_server_add_labels": (C.c_int, [vp, vp, vp]),
             "chl_server_submit_queries": (C.c_int, [vp, i32, vp, vp, i64, vp, vp]),
             "chl_server_submit_build": (C.c_int, [vp, i32, i64, vp, vp, vp, vp, C.c_double, vp, vp, vp]),
+            "chl_server_build_footprint": (C.c_size_t, [vp, i32, i64]),
             "chl_server_start": (C.c_int, [vp]),
             "chl_server_wait": (C.c_int, [vp]),
             "chl_server_labels": (vp, [vp, i32]),
@@ -247,9 +249,10 @@ class Labels:
 
 
 def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, delta=0,
-          early_term=True, stats=True, autotune=True, stream=None, allocator="torch"):
+          early_term=True, stats=True, autotune=True, roots=None, stream=None, allocator="torch"):
     """chl_build over a symmetric CSR (row_ptr int64, col int32, w int32) and a
-    ranking order (order[0] most important). Returns Labels."""
+    ranking order (order[0] most important). roots = (begin, count, stride)
+    restricts the build to those root rank positions. Returns Labels."""
     lib = load()
     rp = _dev(row_ptr, torch.int64)
     cl = _dev(col, torch.int32)
@@ -267,6 +270,8 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
     o.early_term = 1 if early_term else 0
     o.stats = 1 if stats else 0
     o.autotune = 1 if autotune else 0
+    if roots is not None:
+        o.root_begin, o.root_count, o.root_stride = (int(x) for x in roots)
     al = default_allocator() if allocator == "torch" else None
     out = C.c_void_p()
     code = lib.chl_build(C.byref(g), od.data_ptr(), C.byref(o), C.byref(al.c) if al else None,

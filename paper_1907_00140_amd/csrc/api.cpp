@@ -258,16 +258,17 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
     return 0;
 }
 
-int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early, hipStream_t st,
-              int* launches) {
+int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
+              const std::vector<int32_t>& sel, hipStream_t st, int* launches) {
     int grid = plain_grid_size(B.key_bits, wg);
     if (grid <= 0) return CHL_ERR_HIP;
     grid = std::min(grid, std::max(1, (B.n + wg - 1) / wg) * 4);
     const int32_t CH = 1024;
     std::vector<int32_t> todo;
-    for (int32_t r0 = 0; r0 < B.n; r0 += CH) {
+    const int32_t nr = sel.empty() ? B.n : (int32_t)sel.size();
+    for (int32_t r0 = 0; r0 < nr; r0 += CH) {
         todo.clear();
-        for (int32_t r = r0; r < std::min(B.n, r0 + CH); r++) todo.push_back(r);
+        for (int32_t r = r0; r < std::min(nr, r0 + CH); r++) todo.push_back(sel.empty() ? r : sel[r]);
         while (!todo.empty()) {
             HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));
             HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));
@@ -448,6 +449,11 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.wg_size != 0 && o.wg_size != 256 && o.wg_size != 512 && o.wg_size != 1024) return CHL_ERR_INVALID_ARG;
     if (o.mode == CHL_MODE_PLAIN && o.wg_size == 1024) return CHL_ERR_INVALID_ARG;
     if (o.roots_in_flight < 0 || o.delta < 0) return CHL_ERR_INVALID_ARG;
+    if (o.root_count < 0) return CHL_ERR_INVALID_ARG;
+    if (o.root_count > 0) {
+        if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
+        if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;
+    }
     if (int r = check_device()) return r;
     chl_allocator al = alloc_in ? *alloc_in : kDefaultAlloc;
     if (!al.alloc || !al.free) return CHL_ERR_INVALID_ARG;
@@ -531,8 +537,13 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
     int launches = 0;
     Timer ttree(st);
-    int r = o.mode == CHL_MODE_PLAIN ? run_plain(A, B, s, wg, delta, o.early_term, st, &launches)
-                                     : run_batched(A, B, s, wg, delta, o.early_term, nullptr, n, st, &launches);
+    std::vector<int32_t> sel;
+    if (o.root_count > 0)
+        for (int32_t i = 0; i < o.root_count; i++) sel.push_back(o.root_begin + i * o.root_stride);
+    int r = o.mode == CHL_MODE_PLAIN
+                ? run_plain(A, B, s, wg, delta, o.early_term, sel, st, &launches)
+                : run_batched(A, B, s, wg, delta, o.early_term, sel.empty() ? nullptr : sel.data(),
+                              sel.empty() ? n : (int32_t)sel.size(), st, &launches);
     if (r) return r;
     S.tree_ms = ttree.stop();
     S.launches = launches;
@@ -619,9 +630,10 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     // probe: the first roots (largest trees) and a rank-stratified sample
     std::vector<int32_t> probe;
-    int32_t head = std::min<int32_t>(n, 128);
+    // the head trees span the whole graph: fewer of them on large graphs
+    int32_t head = std::min<int32_t>(n, n > (1 << 18) ? 32 : 128);
     for (int32_t r = 0; r < head; r++) probe.push_back(r);
-    int32_t strata = std::min<int32_t>(n - head, 384);
+    int32_t strata = std::min<int32_t>(n - head, n > (1 << 18) ? 256 : 384);
     for (int32_t i = 0; i < strata; i++) probe.push_back(head + (int32_t)((int64_t)(n - head) * i / strata));
     auto t0 = std::chrono::steady_clock::now();
     double best = 1e30;

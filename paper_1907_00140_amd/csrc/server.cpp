@@ -366,6 +366,11 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
     return CHL_OK;
 }
 
+size_t chl_server_build_footprint(const chl_server* s, int32_t n, int64_t n_arcs) {
+    if (!s || n < 1 || n_arcs < 0) return 0;
+    return build_footprint(n, n_arcs, s->o.build_wg);
+}
+
 int chl_server_start(chl_server* s) {
     if (!s || s->running) return CHL_ERR_INVALID_ARG;
     s->running = true;

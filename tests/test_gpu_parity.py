@@ -196,3 +196,67 @@ def test_grid_large_sampled():
     seg_first = np.zeros(len(hub), bool)
     seg_first[off[:-1][np.diff(off) > 0]] = True
     assert (np.diff(hub.astype(np.int64))[~seg_first[1:]] > 0).all()
+
+
+def _sampled_roots_parity(name, head, strata):
+    """Per-root parity on a full-size workload: the GPU builds only the head
+    roots (largest trees) and a rank-stratified sample, with the same launch
+    configuration as a full build; the oracle grows the same trees."""
+    from paper_1907_00140_amd import chl
+    c = gg.make_config(name)
+    n = c["n"]
+    stride = (n - head) // strata
+    for begin, count, step in ((0, head, 1), (head, strata, stride)):
+        roots = [begin + i * step for i in range(count)]
+        _say(name, "gpu roots", begin, count, step)
+        L = chl.build(c["row_ptr"], c["col"], c["w"], c["order"], roots=(begin, count, step))
+        off, hub, dist = (t.numpy() for t in L.export("cpu"))
+        assert L.info()[1] == len(hub)
+        _say(name, "oracle roots")
+        want, wst = oracle.roots(c["row_ptr"], c["col"], c["w"], c["order"], roots)
+        got = per_root_from_export(off, hub, dist, c["order"], roots)
+        assert sum(len(v) for v, _ in want) == len(hub)
+        for r, (v, d) in zip(roots, want):
+            gv, gd = got[int(r)]
+            assert np.array_equal(gv, v) and np.array_equal(gd, d), (name, r)
+        L.free()
+
+
+def test_grid1024d_sampled_roots():
+    _sampled_roots_parity("grid1024d", 48, 160)
+
+
+def test_rmat20_sampled_roots():
+    _sampled_roots_parity("rmat20", 24, 160)
+
+
+def test_grid1024d_full_queries():
+    """Complete labeling of the 1024x1024 grid with shortcuts: every L_v is
+    strictly increasing in hub and holds its self label; queries from sampled
+    sources equal Dijkstra distances (cover property at full size)."""
+    import torch
+    from paper_1907_00140_amd import chl
+    c = gg.make_config("grid1024d")
+    n = c["n"]
+    _say("grid1024d full build")
+    L = chl.build(c["row_ptr"], c["col"], c["w"], c["order"])
+    off, hub, dist = L.export("cuda")
+    pos = torch.empty(n, dtype=torch.int32, device="cuda")
+    pos[torch.from_numpy(c["order"]).long().cuda()] = torch.arange(n, dtype=torch.int32, device="cuda")
+    cnt = off[1:] - off[:-1]
+    assert int(cnt.min()) >= 1
+    first = torch.zeros(hub.numel(), dtype=torch.bool, device="cuda")
+    first[off[:-1]] = True
+    dh = hub[1:].long() - hub[:-1].long()
+    assert bool((dh[~first[1:]] > 0).all())
+    # the last entry of L_v is v itself at distance 0 (no hub ranks below v)
+    last = off[1:] - 1
+    assert bool((hub[last] == pos).all()) and bool((dist[last] == 0).all())
+    g = np.random.default_rng(3)
+    for s in g.choice(n, 6, replace=False):
+        ref = oracle.sssp(c["row_ptr"], c["col"], c["w"], int(s))
+        tgt = g.choice(n, 20000, replace=False).astype(np.int32)
+        pairs = np.stack([np.full(len(tgt), s, np.int32), tgt], 1)
+        q = L.query(pairs).cpu().numpy()
+        assert np.array_equal(q, ref[tgt]), s
+    L.free()

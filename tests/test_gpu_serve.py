@@ -1,0 +1,85 @@
+"""Continuous-batching server: results in the mix equal results alone.
+
+Queries against resident labelings arrive as an open-loop Poisson stream
+while label builds of other graphs arrive, are admitted by their device
+memory footprint and run on their own streams. Every query answer and every
+built labeling must equal what the same request gives on its own (and the
+oracle), bit for bit."""
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+import oracle
+from gpu_util import assert_same_labels
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _resident():
+    from paper_1907_00140_amd import chl
+    out = []
+    for name in ("grid64", "rmat12s9"):
+        c = gg.make_config(name)
+        L = chl.build(c["row_ptr"], c["col"], c["w"], c["order"])
+        out.append((c, L))
+    return out
+
+
+def test_mix_equals_alone():
+    from paper_1907_00140_amd import serve
+    res = _resident()
+    alone = [L.query(c["pairs"]).cpu().numpy() for c, L in res]
+    builds = [(gg.make_config("rmat%d_%d" % (10 + i % 3, i)), 0.01 + 0.02 * i) for i in range(5)]
+    _say("serve mix")
+    srv, tickets, btk, wall = serve.open_loop(
+        lambda: serve.Server(mem_budget=8 << 30, max_batch=4096, build_streams=2, build_wg=64),
+        [L for _, L in res], [c["pairs"] for c, _ in res], rate=2e5, builds=builds, seed=7)
+    for (c, _), tk, ref in zip(res, tickets, alone):
+        assert np.array_equal(tk.out, ref)
+        assert np.isfinite(tk.lat).all() and (tk.lat >= 0).all()
+    for (c, _), tk in zip(builds, btk):
+        assert tk.status.value == 0, tk.status.value
+        assert tk.lat.value > 0
+        L = srv.labels(tk.gid.value)
+        off, hub, dist = L.export("cpu")
+        ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+        assert_same_labels(off.numpy(), hub.numpy(), dist.numpy(), ref, "built in the mix")
+        q = L.query(c["pairs"]).cpu().numpy()
+        assert np.array_equal(q, oracle.query(ref, c["pairs"]))
+    _say("p50 %.1f us p99 %.1f us wall %.3f s" % (np.percentile(tickets[0].lat, 50) * 1e6,
+                                                    np.percentile(tickets[0].lat, 99) * 1e6, wall))
+    srv.close()
+
+
+def test_admission_by_footprint():
+    """A build larger than the whole budget is rejected; builds that fit only
+    one at a time are deferred and still complete."""
+    from paper_1907_00140_amd import serve
+    c = gg.make_config("rmat10_1")
+    srv = serve.Server(mem_budget=1 << 20, build_streams=2, build_wg=64)
+    tk = srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.0)
+    srv.start()
+    srv.wait()
+    assert tk.status.value == -6
+    srv.close()
+    srv = serve.Server(mem_budget=1 << 20, build_streams=2, build_wg=64)
+    fp = srv.footprint(c["n"], len(c["col"]))
+    srv = serve.Server(mem_budget=int(1.5 * fp), build_streams=2, build_wg=64)
+    tks = [srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.001 * i) for i in range(3)]
+    srv.start()
+    srv.wait()
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    lat = sorted(tk.lat.value for tk in tks)
+    assert lat[1] > lat[0] and lat[2] > lat[1]      # one at a time: each waits for the previous
+    for tk in tks:
+        assert tk.status.value == 0
+        off, hub, dist = srv.labels(tk.gid.value).export("cpu")
+        assert_same_labels(off.numpy(), hub.numpy(), dist.numpy(), ref)
+    srv.close()
