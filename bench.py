@@ -34,12 +34,52 @@ def src_sha():
     return hashlib.sha256(open(TREE_SRC, "rb").read()).hexdigest()[:16]
 
 
+def serve_measure(chl, gg, c, row, col, w, order, stream, qout, q):
+    """Open-loop serving on the resident labeling: saturation throughput of
+    the server path, then a Poisson stream at half of it with two label
+    builds of other graphs arriving meanwhile."""
+    import numpy as np
+    from paper_1907_00140_amd import serve
+    L = chl.build(row, col, w, order, stream=stream)
+    sp = np.concatenate([c["pairs"], c["pairs"]])
+    mk = lambda: serve.Server(mem_budget=32 << 30, max_batch=1 << 16, build_streams=2, build_wg=128)
+    srv = mk()
+    gid = srv.add_labels(L)
+    tk = srv.submit_queries(gid, sp, np.zeros(len(sp)))
+    t1 = time.perf_counter()
+    srv.start()
+    srv.wait()
+    sat_qps = len(sp) / (time.perf_counter() - t1)
+    srv.close()
+    rate = 0.5 * sat_qps
+    span = len(sp) / rate
+    blds = [(gg.make_config("rmat12_0"), 0.2 * span), (gg.make_config("rmat13_1"), 0.5 * span)]
+    srv, tks, btk, wall = serve.open_loop(mk, [L], [sp], rate, builds=blds, seed=11)
+    lat = tks[0].lat
+    assert np.array_equal(tks[0].out[:q], qout.cpu().numpy())
+    serving = {"resident": "R-MAT scale 16 labeling", "queries": int(len(sp)),
+           "saturated_qps": round(sat_qps, 1), "rate_qps": round(rate, 1),
+           "achieved_qps": round(len(sp) / float(np.max(tks[0].t + lat)), 1),
+           "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 2),
+           "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 2),
+           "builds": [{"graph": nm, "status": int(b.status.value), "latency_s": round(b.lat.value, 4)}
+                      for (cc, _), b, nm in zip(blds, btk, ("rmat12_0", "rmat13_1"))]}
+    srv.close()
+    L.free()
+
+    return serving
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-form estimate")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -54,6 +94,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     c = gg.make_config(WORKLOAD)
     counts = json.load(open(COUNTS))[WORKLOAD]
     A, S, Lc = counts["arcs"], counts["settled"], counts["labels"]
@@ -120,45 +166,21 @@ def main():
     H, NS = 64, 256
     stride = (n - H) // NS
     tp = []
-    for roots in ((0, H, 1), (H, NS, stride)):
+    for roots in ((0, H, 1), (H, NS, stride)) if not args.no_plain else ():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         Lp = chl.build(row, col, w, order, mode="plain", roots=roots, stream=stream)
         torch.cuda.synchronize()
         tp.append(time.perf_counter() - t1)
         Lp.free()
-    plain_est_s = tp[0] + tp[1] * stride
+    plain_est_s = tp[0] + tp[1] * stride if tp else None
 
     # open-loop serving on the resident labeling: saturation throughput of the
     # server path, then a Poisson stream at half of it with two label builds
     # of other graphs arriving meanwhile
-    from paper_1907_00140_amd import serve
-    L = chl.build(row, col, w, order, stream=stream)
-    sp = np.concatenate([c["pairs"], c["pairs"]])
-    mk = lambda: serve.Server(mem_budget=32 << 30, max_batch=1 << 16, build_streams=2, build_wg=128)
-    srv = mk()
-    gid = srv.add_labels(L)
-    tk = srv.submit_queries(gid, sp, np.zeros(len(sp)))
-    t1 = time.perf_counter()
-    srv.start()
-    srv.wait()
-    sat_qps = len(sp) / (time.perf_counter() - t1)
-    srv.close()
-    rate = 0.5 * sat_qps
-    span = len(sp) / rate
-    blds = [(gg.make_config("rmat12_0"), 0.2 * span), (gg.make_config("rmat13_1"), 0.5 * span)]
-    srv, tks, btk, wall = serve.open_loop(mk, [L], [sp], rate, builds=blds, seed=11)
-    lat = tks[0].lat
-    assert np.array_equal(tks[0].out[:q], qout.cpu().numpy())
-    serving = {"resident": "R-MAT scale 16 labeling", "queries": int(len(sp)),
-               "saturated_qps": round(sat_qps, 1), "rate_qps": round(rate, 1),
-               "achieved_qps": round(len(sp) / wall, 1),
-               "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 2),
-               "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 2),
-               "builds": [{"graph": nm, "status": int(b.status.value), "latency_s": round(b.lat.value, 4)}
-                          for (cc, _), b, nm in zip(blds, btk, ("rmat12_0", "rmat13_1"))]}
-    srv.close()
-    L.free()
+    serving = {"p50_us": None, "p99_us": None}
+    if not args.no_serve:
+        serving = serve_measure(chl, gg, c, row, col, w, order, stream, qout, q)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -182,9 +204,9 @@ def main():
                    "delta": stats["delta"], "key_bits": stats["key_bits"]},
         "build_s": round(b_s, 4), "queries_per_s": round(qps, 1), "labels": Lc,
         "p50_us": serving["p50_us"], "p99_us": serving["p99_us"],
-        "plain_form": {"build_s_est": round(plain_est_s, 3), "gteps_est": round(A / plain_est_s / 1e9, 4),
-                       "method": "64 head roots + 256 rank-stratified roots (stride %d), sum = head + sample * stride"
-                                 % stride},
+        "plain_form": None if plain_est_s is None else {
+            "build_s_est": round(plain_est_s, 3), "gteps_est": round(A / plain_est_s / 1e9, 4),
+            "method": "64 head roots + 256 rank-stratified roots (stride %d), sum = head + sample * stride" % stride},
         "serving": serving,
         "gpu_arcs": stats["arcs"], "oracle_arcs": A, "work_inflation": round(stats["arcs"] / A, 3),
         "roofline": roofline, "cpu_baseline": cpu,

@@ -204,7 +204,8 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
 // Run the batched kernel over roots (NULL = all, in rank order) until every
 // root has emitted, growing the pool when it fills up.
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
-                const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches) {
+                const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
+                bool probe = false) {
     std::vector<int32_t> pending;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
@@ -215,7 +216,7 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
         HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
         TreeParams p = params(B, s, delta, early, dev_roots, nroots);
-        if (launch_tree_batched(p, B.key_bits, wg, st)) return CHL_ERR_HIP;
+        if (launch_tree_batched(p, B.key_bits, wg, probe, st)) return CHL_ERR_HIP;
         (*launches)++;
         int32_t c32[4];
         unsigned long long c64[2];
@@ -653,7 +654,9 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         }
         HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
         Timer t(st);
-        if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st, &launches)) return r;
+        if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st,
+                                &launches, true))
+            return r;
         double ms = t.stop();
         seen[{kk, w, d}] = ms;
         if (ms < best) { best = ms; bv = TuneVal{kk, w, d}; }

@@ -106,7 +106,7 @@ int launch_segsort_u64(uint64_t* keys, const int64_t* off, int64_t nseg, int64_t
                        void* temp, hipStream_t st);
 
 // tree.hip
-int launch_tree_batched(const TreeParams& p, int key_bits, int wg, hipStream_t st);
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, bool probe, hipStream_t st);
 int launch_tree_plain(const TreeParams& p, int key_bits, int wg, int grid, int32_t root,
                       int32_t* gstate, hipStream_t st);
 int plain_grid_size(int key_bits, int wg);

@@ -271,7 +271,9 @@ __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, con
     return cl == 0 && lb > S.umax;
 }
 
-template <typename K, int WG>
+// PROBE = 1 instantiates the same kernel under its own symbol for the
+// autotuner's probe runs, so profiles of complete builds see only them.
+template <typename K, int WG, int PROBE>
 __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
     __shared__ BatchedLds<K, WG> S;
@@ -625,8 +627,11 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
 }
 
 template <typename K, int WG>
-int launch_batched_t(const TreeParams& p, hipStream_t st) {
-    hipLaunchKernelGGL((k_tree_batched<K, WG>), dim3(p.s.k), dim3(WG), 0, st, p);
+int launch_batched_t(const TreeParams& p, bool probe, hipStream_t st) {
+    if (probe)
+        hipLaunchKernelGGL((k_tree_batched<K, WG, 1>), dim3(p.s.k), dim3(WG), 0, st, p);
+    else
+        hipLaunchKernelGGL((k_tree_batched<K, WG, 0>), dim3(p.s.k), dim3(WG), 0, st, p);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -651,15 +656,15 @@ int plain_grid_t() {
 
 }  // namespace
 
-int launch_tree_batched(const TreeParams& p, int key_bits, int wg, hipStream_t st) {
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, bool probe, hipStream_t st) {
     if (key_bits == 32) {
-        if (wg == 256) return launch_batched_t<uint32_t, 256>(p, st);
-        if (wg == 512) return launch_batched_t<uint32_t, 512>(p, st);
-        if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, st);
+        if (wg == 256) return launch_batched_t<uint32_t, 256>(p, probe, st);
+        if (wg == 512) return launch_batched_t<uint32_t, 512>(p, probe, st);
+        if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, probe, st);
     } else {
-        if (wg == 256) return launch_batched_t<uint64_t, 256>(p, st);
-        if (wg == 512) return launch_batched_t<uint64_t, 512>(p, st);
-        if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, st);
+        if (wg == 256) return launch_batched_t<uint64_t, 256>(p, probe, st);
+        if (wg == 512) return launch_batched_t<uint64_t, 512>(p, probe, st);
+        if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, probe, st);
     }
     return -1;
 }
