@@ -122,7 +122,7 @@ def main():
         assert L.info()[1] == Lc, "label count differs from the oracle's"
         L.free()
     torch.cuda.synchronize()
-    build_ms, query_ms, tree_ms, launches, stats = [], [], [], [], None
+    build_ms, query_ms, kernel_ms, klaunch, stats = [], [], [], [], None
     t0 = time.perf_counter()
     for _ in range(args.steps):
         tb = time.perf_counter()
@@ -134,9 +134,11 @@ def main():
         te = time.perf_counter()
         build_ms.append((tq - tb) * 1e3)
         query_ms.append((te - tq) * 1e3)
-        stats = L.stats()
-        tree_ms.append(stats["tree_ms"])
-        launches.append(stats["launches"])
+        stats = L.stats(per_root=True)
+        per_root = stats.pop("per_root")
+        gpu_arcs = int(per_root[:, 1].sum())
+        kernel_ms.append(stats["kernel_ms"])
+        klaunch.append(stats["kernel_launches"])
         L.free()
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t0
@@ -144,11 +146,24 @@ def main():
     gteps = A / b_s / 1e9
     qps = q / (float(np.median(query_ms)) / 1e3)
 
-    # roofline of the dominant kernel (batched tree kernel): algorithmic bytes
-    # 16 per scanned arc + 16 per settled vertex + 8 per label (oracle counts)
-    alg_bytes = 16 * A + 16 * S + 8 * Lc
-    per_launch_ms = float(np.median(tree_ms)) / max(1, int(np.median(launches)))
-    achieved = alg_bytes / max(1, int(np.median(launches))) / (per_launch_ms / 1e3) / 1e9
+    # roofline of the dominant kernel, the batched tree kernel: all its
+    # production launches of one build (the prefix levels and the main
+    # phase), timed with events on the build stream inside the library.
+    # Algorithmic bytes = 16 per scanned arc + 16 per settled vertex + 8 per
+    # label, with the units counted by the oracle's trees under the same
+    # pruning configuration (tests/golden/workload_counts.json)
+    g, pm = stats["prefix_roots"], stats["prune_hubs"]
+    if g == 0:
+        cfg = None
+        units = {"arcs": A, "settled": S, "labels": Lc}
+    else:
+        cfg = next(v for k, v in counts.items() if isinstance(v, dict) and v.get("grown") == g
+                   and v.get("pmain") == pm)
+        units = {k: cfg["head"][k] + cfg["rest"][k] for k in ("arcs", "settled", "labels")}
+    nl = max(1, int(np.median(klaunch)))
+    alg_bytes = (16 * units["arcs"] + 16 * units["settled"] + 8 * units["labels"]) / nl
+    per_launch_ms = float(np.median(kernel_ms)) / nl
+    achieved = alg_bytes / (per_launch_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC):
         tr = json.load(open(TRAFFIC))
@@ -156,8 +171,27 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_tree_batched", "kernel_ms": round(per_launch_ms, 3),
-                "alg_bytes_per_launch": alg_bytes / max(1, int(np.median(launches)))}
+                "kernel": "k_tree_batched (production launches: prefix levels + main phase)",
+                "kernel_ms": round(per_launch_ms, 3), "launches_per_build": nl,
+                "alg_bytes_per_launch": alg_bytes,
+                "units_per_build": units}
+
+    # the same batched build without the common label table (PLaNT trees
+    # alone, Section 4.2), for reference
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Lu = chl.build(row, col, w, order, prune_hubs=-1, stream=stream)
+    torch.cuda.synchronize()
+    unpruned_s = time.perf_counter() - t1
+    unpruned_arcs = Lu.stats()["arcs"]
+    Lu.free()
+    # the unpruned build is tuned on its first call; time it again
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Lu = chl.build(row, col, w, order, prune_hubs=-1, stream=stream)
+    torch.cuda.synchronize()
+    unpruned_s = time.perf_counter() - t1
+    Lu.free()
 
     # plain form (one root per cooperative launch, the whole device on one
     # tree): time the 64 head roots and a rank-stratified sample of 256 of
@@ -201,14 +235,22 @@ def main():
         "config": {"workload": "R-MAT scale 16 (65,536 vertices, %d edges), int32 weights [1,1000], degree rank; "
                                "full canonical labeling + 10^6 uniform queries" % c["m"],
                    "mode": "batched", "roots_in_flight": stats["roots_in_flight"], "wg_size": stats["wg_size"],
-                   "delta": stats["delta"], "key_bits": stats["key_bits"]},
+                   "delta": stats["delta"], "key_bits": stats["key_bits"], "prune_hubs": stats["prune_hubs"]},
         "build_s": round(b_s, 4), "queries_per_s": round(qps, 1), "labels": Lc,
         "p50_us": serving["p50_us"], "p99_us": serving["p99_us"],
+        "batched_unpruned": {"build_s": round(unpruned_s, 4), "gteps": round(A / unpruned_s / 1e9, 4),
+                             "gpu_arcs": unpruned_arcs},
         "plain_form": None if plain_est_s is None else {
             "build_s_est": round(plain_est_s, 3), "gteps_est": round(A / plain_est_s / 1e9, 4),
             "method": "64 head roots + 256 rank-stratified roots (stride %d), sum = head + sample * stride" % stride},
         "serving": serving,
-        "gpu_arcs": stats["arcs"], "oracle_arcs": A, "work_inflation": round(stats["arcs"] / A, 3),
+        "gpu_arcs": gpu_arcs,
+        "oracle_arcs_unpruned": A,
+        "oracle_arcs_method": units["arcs"],
+        "method_gteps": round(units["arcs"] / b_s / 1e9, 4),
+        "work_inflation": round(gpu_arcs / max(1, units["arcs"]), 3),
+        "phases_ms": {"prep": round(stats["prep_ms"], 3), "prefix": round(stats["prefix_ms"], 3),
+                      "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -113,6 +113,18 @@ typedef struct chl_build_opts {
                                 them (trees are independent, Section 4.2) */
     int32_t root_begin;
     int32_t root_stride;     /* >= 1 when root_count > 0 */
+    int32_t prune_hubs;      /* batched form: rank-prefix pruning (Section 4.3).
+                                The trees of roots [0, 16) grow first; each
+                                later level of roots [g, 8g) is pruned by the
+                                labels of the hubs [0, g) (complete by then),
+                                up to a prefix of prune_hubs hubs (<= 4096);
+                                every other tree is pruned by that prefix. A
+                                relaxation is dropped when a walk through a
+                                prefix hub is no longer. Same labels either
+                                way. > 0: that prefix size; 0: 4096, kept only
+                                if the 16-hub level speeds up a probe of later
+                                trees (always kept when autotune is 0); < 0:
+                                off. Ignored by the plain form. */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */
@@ -166,8 +178,18 @@ typedef struct chl_stats {
     int64_t roots_in_flight; /* parameters actually used */
     int64_t wg_size;
     int64_t delta;
-    int64_t launches;        /* kernel launches of the tree phase */
-    double tree_ms;          /* device time of the tree phase */
+    int64_t prune_hubs;      /* size of the pruning prefix of the main phase (0: none) */
+    int64_t prefix_roots;    /* roots grown before the main phase (0: none) */
+    int64_t launches;        /* kernel launches of the main tree phase */
+    int64_t clock_khz;       /* device wall clock of the per-root tick counts */
+    double tree_ms;          /* device time of the main tree phase (every root
+                                not grown for the common label table) */
+    double prefix_ms;        /* trees of the prefix levels and their regrouping */
+    double kernel_ms;        /* device time of every tree-kernel launch of the
+                                build (prefix levels and main phase; excludes
+                                the autotuner's and the pruning decision's
+                                probes) */
+    int64_t kernel_launches; /* number of those launches */
     double assemble_ms;      /* device time of label assembly */
     double prep_ms;          /* validation + rank renumbering */
     double tune_ms;          /* autotuner probe time (0 when cached or off) */

@@ -51,6 +51,9 @@ def load(path=None):
     vp = C.c_void_p
     lib.oracle_run_roots.restype = vp
     lib.oracle_run_roots.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int]
+    lib.oracle_run_roots_levels.restype = vp
+    lib.oracle_run_roots_levels.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32,
+                                            C.c_int32, C.c_int]
     lib.oracle_run_count.restype = C.c_int64
     lib.oracle_run_count.argtypes = [vp, C.c_int64]
     lib.oracle_run_total.restype = C.c_int64
@@ -114,6 +117,40 @@ def chl(row_ptr, col, w, order, mode=MODE_PLANT, threads=None, lib=None):
     finally:
         lib.oracle_run_free(h)
     return Labels(offsets, hub[:total], dist[:total], stats)
+
+
+def _assemble(lib, h, n):
+    try:
+        total = lib.oracle_run_total(h)
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        hub = np.zeros(max(total, 1), dtype=np.int32)
+        dist = np.zeros(max(total, 1), dtype=np.int64)
+        lib.oracle_run_assemble(h, offsets.ctypes.data, hub.ctypes.data, dist.ctypes.data)
+        stats = np.zeros((n, 4), dtype=np.int64)
+        lib.oracle_run_stats(h, stats.ctypes.data)
+    finally:
+        lib.oracle_run_free(h)
+    return Labels(offsets, hub[:total], dist[:total], stats)
+
+
+def chl_pruned(row_ptr, col, w, order, eta=None, grown=None, levels=None, pmain=None, threads=None,
+               lib=None):
+    """Complete CHL by PLaNT trees with rank-prefix pruning (Section 4.3),
+    grown in levels: ``levels`` = [g_0, g_1, ...]: roots [0, g_0) unpruned,
+    level [g_{j-1}, g_j) pruned by the labels of hubs [0, g_{j-1}), and every
+    later root pruned by hubs [0, pmain). ``eta, grown`` is the one-level
+    case (levels=[grown], pmain=eta). Same labels as chl(); different work
+    counts (stats, indexed by root rank position)."""
+    lib = lib or load()
+    if levels is None:
+        levels, pmain = [grown], eta
+    row_ptr, col, w, order = _graph_args(row_ptr, col, w, order)
+    n = len(row_ptr) - 1
+    lv = np.ascontiguousarray(levels, dtype=np.int32)
+    threads = threads or min(16, os.cpu_count() or 1)
+    h = lib.oracle_run_roots_levels(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                                    order.ctypes.data, None, 0, lv.ctypes.data, len(lv), int(pmain), threads)
+    return _assemble(lib, h, n)
 
 
 def roots(row_ptr, col, w, order, root_pos, mode=MODE_PLANT, threads=None, lib=None):

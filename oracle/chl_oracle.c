@@ -177,11 +177,55 @@ static inline int32_t top_of(const int32_t* pos, int32_t x, int32_t y) {
     return pos[x] < pos[y] ? x : y;
 }
 
-/* (2) PLaNTDijkstra (Algorithm 3) with the readings stated above. */
+/* Prefix labels used for pruning (Section 4.3): for every vertex, its labels
+ * whose hub has rank position < e, sorted by hub; all of them are final once
+ * the trees of the roots at rank positions < e are done. */
+typedef struct {
+    int32_t e;
+    int64_t* off;      /* [n+1] */
+    int32_t* hub;      /* rank positions */
+    int64_t* dist;
+} prefix_t;
+
+/* Length of the shortest root-u walk through a hub of the prefix: the
+ * minimum of d(h,x) + d(x,u) over prefix hubs x in both label sets
+ * (INF64 if none). */
+static int64_t prefix_query(const prefix_t* P, int32_t h, int32_t u) {
+    int64_t i = P->off[h], ie = P->off[h + 1], j = P->off[u], je = P->off[u + 1];
+    int64_t best = INF64;
+    while (i < ie && j < je) {
+        if (P->hub[i] < P->hub[j]) i++;
+        else if (P->hub[i] > P->hub[j]) j++;
+        else {
+            int64_t s = P->dist[i] + P->dist[j];
+            if (s < best) best = s;
+            i++; j++;
+        }
+    }
+    return best;
+}
+
+/* (2) PLaNTDijkstra (Algorithm 3) with the readings stated above. With a
+ * prefix P (roots below P->e done, h not among them), a relaxation whose
+ * tentative distance is not below the prefix query of (h, u) is skipped:
+ * such a candidate is either not shortest or runs through a prefix hub,
+ * which outranks h, so it cannot produce a label (Section 4.3). */
+static int64_t plant_tree_p(ws_t* w, const int64_t* row_ptr, const int32_t* col,
+                            const int32_t* wt, const int32_t* pos, int32_t h,
+                            int early_term, const prefix_t* P, int32_t* out_v, int64_t* out_d,
+                            tree_stats* st);
+
 int64_t oracle_plant_tree(ws_t* w, const int64_t* row_ptr, const int32_t* col,
                           const int32_t* wt, const int32_t* pos, int32_t h,
                           int early_term, int32_t* out_v, int64_t* out_d,
                           tree_stats* st) {
+    return plant_tree_p(w, row_ptr, col, wt, pos, h, early_term, NULL, out_v, out_d, st);
+}
+
+static int64_t plant_tree_p(ws_t* w, const int64_t* row_ptr, const int32_t* col,
+                            const int32_t* wt, const int32_t* pos, int32_t h,
+                            int early_term, const prefix_t* P, int32_t* out_v, int64_t* out_d,
+                            tree_stats* st) {
     int64_t* delta = w->dist;
     int32_t* a = w->anc;
     int64_t nl = 0, npop = 0, arcs = 0, cnt;
@@ -206,6 +250,7 @@ int64_t oracle_plant_tree(ws_t* w, const int64_t* row_ptr, const int32_t* col,
             int64_t nd = delta[v] + wt[e];
             int32_t pA = a[u];
             arcs++;
+            if (P && nd <= delta[u] && prefix_query(P, h, u) <= nd) continue;   /* pruned */
             if (nd < delta[u]) a[u] = top_of(pos, nA, u);
             else if (nd == delta[u]) a[u] = top_of(pos, nA, pA);
             if (a[u] == h && pA != h) cnt++;
@@ -228,6 +273,7 @@ typedef struct {
     const int64_t* row_ptr; const int32_t* col; const int32_t* wt;
     int32_t* pos; const int32_t* order;
     int mode;                       /* 0 definition, 1 PLaNT + early term, 2 PLaNT without */
+    const prefix_t* prefix;         /* pruning labels, or NULL */
     const int32_t* roots; int64_t nroots;   /* root rank positions to run */
     _Atomic int64_t next;
     int32_t** lv; int64_t** ld; int64_t* cnt;  /* per task (index into roots) */
@@ -246,7 +292,8 @@ static void* worker(void* arg) {
         tree_stats st;
         int64_t nl = J->mode == 0
             ? oracle_def_tree(w, J->row_ptr, J->col, J->wt, J->pos, h, bv, bd, &st)
-            : oracle_plant_tree(w, J->row_ptr, J->col, J->wt, J->pos, h, J->mode == 1, bv, bd, &st);
+            : plant_tree_p(w, J->row_ptr, J->col, J->wt, J->pos, h, J->mode == 1,
+                           J->prefix && J->pos[h] >= J->prefix->e ? J->prefix : NULL, bv, bd, &st);
         J->lv[t] = (int32_t*)malloc((size_t)(nl ? nl : 1) * sizeof(int32_t));
         J->ld[t] = (int64_t*)malloc((size_t)(nl ? nl : 1) * sizeof(int64_t));
         memcpy(J->lv[t], bv, (size_t)nl * sizeof(int32_t));
@@ -273,10 +320,10 @@ static int32_t* make_pos(int32_t n, const int32_t* order) {
 
 /* Run the trees of the given root rank positions (roots == NULL: all, in
  * rank order). Returns a handle holding per-root labels and statistics. */
-oracle_run* oracle_run_roots(int32_t n, const int64_t* row_ptr, const int32_t* col,
-                             const int32_t* wt, const int32_t* order,
-                             const int32_t* roots, int64_t nroots, int mode,
-                             int nthreads) {
+static oracle_run* run_roots_p(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                               const int32_t* wt, const int32_t* order,
+                               const int32_t* roots, int64_t nroots, int mode,
+                               int nthreads, const prefix_t* prefix) {
     oracle_run* R = (oracle_run*)calloc(1, sizeof(oracle_run));
     R->n = n;
     if (!roots) nroots = n;
@@ -290,6 +337,7 @@ oracle_run* oracle_run_roots(int32_t n, const int64_t* row_ptr, const int32_t* c
     job_t J = {0};
     J.n = n; J.row_ptr = row_ptr; J.col = col; J.wt = wt; J.order = order;
     J.pos = make_pos(n, order); J.mode = mode; J.roots = R->roots; J.nroots = nroots;
+    J.prefix = prefix;
     atomic_init(&J.next, 0);
     J.lv = R->lv; J.ld = R->ld; J.cnt = R->cnt; J.stats = R->stats;
     if (nthreads < 1) nthreads = 1;
@@ -298,6 +346,13 @@ oracle_run* oracle_run_roots(int32_t n, const int64_t* row_ptr, const int32_t* c
     for (int i = 0; i < nthreads; i++) pthread_join(th[i], NULL);
     free(th); free(J.pos);
     return R;
+}
+
+oracle_run* oracle_run_roots(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                             const int32_t* wt, const int32_t* order,
+                             const int32_t* roots, int64_t nroots, int mode,
+                             int nthreads) {
+    return run_roots_p(n, row_ptr, col, wt, order, roots, nroots, mode, nthreads, NULL);
 }
 
 int64_t oracle_run_count(const oracle_run* R, int64_t t) { return R->cnt[t]; }
@@ -356,6 +411,113 @@ void oracle_run_free(oracle_run* R) {
     if (!R) return;
     for (int64_t t = 0; t < R->nroots; t++) { free(R->lv[t]); free(R->ld[t]); }
     free(R->lv); free(R->ld); free(R->cnt); free(R->stats); free(R->roots); free(R);
+}
+
+/* Prefix labels of hubs [0, e) from a run whose task t is the root of rank
+ * position t (t < e): appended in hub order, so every list is sorted. */
+static void prefix_build(prefix_t* P, int32_t n, int32_t e, int32_t** lv, int64_t** ld,
+                         const int64_t* cnt) {
+    P->e = e;
+    P->off = (int64_t*)calloc((size_t)n + 1, sizeof(int64_t));
+    for (int32_t t = 0; t < e; t++)
+        for (int64_t i = 0; i < cnt[t]; i++) P->off[lv[t][i] + 1]++;
+    for (int32_t v = 0; v < n; v++) P->off[v + 1] += P->off[v];
+    int64_t tot = P->off[n];
+    P->hub = (int32_t*)malloc((size_t)(tot ? tot : 1) * sizeof(int32_t));
+    P->dist = (int64_t*)malloc((size_t)(tot ? tot : 1) * sizeof(int64_t));
+    int64_t* fill = (int64_t*)calloc((size_t)n, sizeof(int64_t));
+    for (int32_t t = 0; t < e; t++)
+        for (int64_t i = 0; i < cnt[t]; i++) {
+            int32_t v = lv[t][i];          /* input id, as the query indexes it */
+            int64_t k = P->off[v] + fill[v]++;
+            P->hub[k] = t;
+            P->dist[k] = ld[t][i];
+        }
+    free(fill);
+}
+
+static void prefix_free(prefix_t* P) { free(P->off); free(P->hub); free(P->dist); }
+
+/* Trees with rank-prefix pruning (Section 4.3), grown in levels. bounds =
+ * g_0 < g_1 < ... < g_L: the roots at rank positions [0, g_0) grow without
+ * pruning; the roots of level [g_{j-1}, g_j) are pruned by the labels of the
+ * hubs [0, g_{j-1}), complete by then; every root at rank position >= g_L is
+ * pruned by the hubs [0, pmain) (pmain <= g_L; 0 = no pruning). Returns a run
+ * over the requested roots (NULL = all roots in rank order). PLaNT with early
+ * termination throughout. */
+oracle_run* oracle_run_roots_levels(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                                    const int32_t* wt, const int32_t* order,
+                                    const int32_t* roots, int64_t nroots,
+                                    const int32_t* bounds, int32_t nb, int32_t pmain,
+                                    int nthreads) {
+    int32_t gl = nb > 0 ? bounds[nb - 1] : 0;
+    if (gl > n) gl = n;
+    if (gl < 0) gl = 0;
+    if (pmain > gl) pmain = gl;
+    /* rank positions [0, gl), level by level */
+    int32_t** lv = (int32_t**)calloc((size_t)(gl ? gl : 1), sizeof(int32_t*));
+    int64_t** ld = (int64_t**)calloc((size_t)(gl ? gl : 1), sizeof(int64_t*));
+    int64_t* cnt = (int64_t*)calloc((size_t)(gl ? gl : 1), sizeof(int64_t));
+    tree_stats* hst = (tree_stats*)calloc((size_t)(gl ? gl : 1), sizeof(tree_stats));
+    int32_t lo = 0;
+    for (int32_t j = 0; j < nb && lo < gl; j++) {
+        int32_t hi = bounds[j] < gl ? bounds[j] : gl;
+        if (hi <= lo) continue;
+        int32_t* lvl = (int32_t*)malloc((size_t)(hi - lo) * sizeof(int32_t));
+        for (int32_t r = lo; r < hi; r++) lvl[r - lo] = r;
+        prefix_t P;
+        int pr = j > 0;
+        if (pr) prefix_build(&P, n, lo, lv, ld, cnt);
+        oracle_run* R = run_roots_p(n, row_ptr, col, wt, order, lvl, hi - lo, 1, nthreads, pr ? &P : NULL);
+        for (int32_t r = lo; r < hi; r++) {
+            lv[r] = R->lv[r - lo]; ld[r] = R->ld[r - lo]; cnt[r] = R->cnt[r - lo]; hst[r] = R->stats[r - lo];
+            R->lv[r - lo] = NULL; R->ld[r - lo] = NULL;
+        }
+        oracle_run_free(R);
+        if (pr) prefix_free(&P);
+        free(lvl);
+        lo = hi;
+    }
+    /* requested roots: those below gl come from the levels, the rest grow now */
+    if (!roots) nroots = n;
+    int32_t* req = (int32_t*)malloc((size_t)(nroots ? nroots : 1) * sizeof(int32_t));
+    int32_t* late = (int32_t*)malloc((size_t)(nroots ? nroots : 1) * sizeof(int32_t));
+    int64_t nlate = 0;
+    for (int64_t i = 0; i < nroots; i++) {
+        req[i] = roots ? roots[i] : (int32_t)i;
+        if (req[i] >= gl) late[nlate++] = req[i];
+    }
+    prefix_t P;
+    if (pmain > 0) prefix_build(&P, n, pmain, lv, ld, cnt);
+    oracle_run* L = run_roots_p(n, row_ptr, col, wt, order, late, nlate, 1, nthreads, pmain > 0 ? &P : NULL);
+    oracle_run* R = (oracle_run*)calloc(1, sizeof(oracle_run));
+    R->n = n; R->nroots = nroots;
+    R->roots = req;
+    R->lv = (int32_t**)calloc((size_t)(nroots ? nroots : 1), sizeof(int32_t*));
+    R->ld = (int64_t**)calloc((size_t)(nroots ? nroots : 1), sizeof(int64_t*));
+    R->cnt = (int64_t*)calloc((size_t)(nroots ? nroots : 1), sizeof(int64_t));
+    R->stats = (tree_stats*)calloc((size_t)(nroots ? nroots : 1), sizeof(tree_stats));
+    int64_t li = 0;
+    for (int64_t i = 0; i < nroots; i++) {
+        int32_t r = req[i];
+        if (r >= gl) {
+            R->lv[i] = L->lv[li]; R->ld[i] = L->ld[li]; R->cnt[i] = L->cnt[li]; R->stats[i] = L->stats[li];
+            L->lv[li] = NULL; L->ld[li] = NULL;
+            li++;
+        } else {
+            /* a copy, since a root may be requested twice */
+            R->cnt[i] = cnt[r]; R->stats[i] = hst[r];
+            R->lv[i] = (int32_t*)malloc((size_t)(cnt[r] ? cnt[r] : 1) * sizeof(int32_t));
+            R->ld[i] = (int64_t*)malloc((size_t)(cnt[r] ? cnt[r] : 1) * sizeof(int64_t));
+            memcpy(R->lv[i], lv[r], (size_t)cnt[r] * sizeof(int32_t));
+            memcpy(R->ld[i], ld[r], (size_t)cnt[r] * sizeof(int64_t));
+        }
+    }
+    oracle_run_free(L);
+    if (pmain > 0) prefix_free(&P);
+    for (int32_t r = 0; r < gl; r++) { free(lv[r]); free(ld[r]); }
+    free(lv); free(ld); free(cnt); free(hst); free(late);
+    return R;
 }
 
 /* ---------------- queries ---------------- */

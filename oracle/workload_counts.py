@@ -20,15 +20,40 @@ import oracle  # noqa: E402
 OUT = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
 
 
+def _sums(st, lo, hi):
+    """Work totals of the roots at rank positions [lo, hi)."""
+    return {"arcs": int(st[lo:hi, 1].sum()), "settled": int(st[lo:hi, 0].sum()),
+            "labels": int(st[lo:hi, 2].sum()), "early_trees": int(st[lo:hi, 3].sum())}
+
+
+LEVELS = [16, 128, 1024, 4096]
+
+
 def counts(name, threads=None):
+    """Unpruned totals, and the work split (roots grown before the main
+    phase / main phase) of each configuration the library's batched build
+    can run: no pruning ("unpruned"), the 16 unpruned probe-level roots
+    followed by unpruned trees ("split16"), and pruning in levels
+    16, 128, 1024, 4096 with the main phase pruned by the 4096-hub
+    prefix ("levels4096")."""
     c = gg.make_config(name)
     t = time.time()
     lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], mode=oracle.MODE_PLANT, threads=threads)
     el = time.time() - t
     st = lab.stats
-    return {"n": int(c["n"]), "m": int(c["m"]), "arcs": int(st[:, 1].sum()), "settled": int(st[:, 0].sum()),
-            "labels": int(lab.total), "early_trees": int(st[:, 3].sum()), "oracle_s": round(el, 2),
-            "threads": threads or min(16, os.cpu_count() or 1)}
+    n = len(st)
+    out = {"n": int(c["n"]), "m": int(c["m"]), "oracle_s": round(el, 2),
+           "threads": threads or min(16, os.cpu_count() or 1), **_sums(st, 0, n),
+           "split16": {"grown": 16, "pmain": 0, "head": _sums(st, 0, 16), "rest": _sums(st, 16, n)}}
+    gmax = min(LEVELS[-1], n // 2)
+    lv = [g for g in LEVELS if g < gmax] + [gmax]
+    if lv:
+        p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1], threads=threads)
+        assert p.total == lab.total
+        out["levels%d" % lv[-1]] = {"grown": lv[-1], "pmain": lv[-1], "head": _sums(p.stats, 0, lv[-1]),
+                                    "rest": _sums(p.stats, lv[-1], n),
+                                    "levels": [[a, b, _sums(p.stats, a, b)] for a, b in zip([0] + lv[:-1], lv)]}
+    return out
 
 
 if __name__ == "__main__":

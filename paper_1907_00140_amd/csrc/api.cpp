@@ -111,6 +111,7 @@ struct TuneKey {
 struct TuneVal {
     int k, wg;
     int64_t delta;
+    int32_t eta;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -131,6 +132,14 @@ struct Build {
     int32_t* gstate = nullptr;         // plain form state words
     Pool pool{};
     int64_t* stats = nullptr;
+    // rank-prefix pruning: labels found so far, by rank position, sorted
+    const int64_t* poff = nullptr;
+    const uint64_t* plab = nullptr;
+    int32_t pbound = 0;                  // prune with the hubs [0, pbound)
+    unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
+    int32_t grown = 0;                   // roots [0, grown) done before the main phase
+    double kernel_ms = 0;                // event-timed production tree launches
+    int64_t kernel_launches = 0;
 };
 
 size_t slot_bytes(int32_t n, int key_bits) {
@@ -182,7 +191,7 @@ int grow_pool(Arena& A, Build& B, unsigned long long used, unsigned long long wa
 }
 
 TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int32_t* roots,
-                  int32_t nroots) {
+                  int32_t nroots, int32_t root_base = 0) {
     TreeParams p{};
     p.g = B.g;
     p.s = s;
@@ -198,6 +207,10 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.nroots = nroots;
     p.roots = roots;
     p.stats = B.stats;
+    p.root_base = root_base;
+    p.poff = B.poff;
+    p.plab = B.plab;
+    p.pbound = B.pbound;
     return p;
 }
 
@@ -205,7 +218,7 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
 // root has emitted, growing the pool when it fills up.
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
                 const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
-                bool probe = false) {
+                int phase = 0, int32_t root_base = 0) {
     std::vector<int32_t> pending;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
@@ -215,8 +228,13 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
     for (;;) {
         HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
         HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
-        TreeParams p = params(B, s, delta, early, dev_roots, nroots);
-        if (launch_tree_batched(p, B.key_bits, wg, probe, st)) return CHL_ERR_HIP;
+        TreeParams p = params(B, s, delta, early, dev_roots, nroots, root_base);
+        {
+            Timer tk(st);
+            if (launch_tree_batched(p, B.key_bits, wg, phase, st)) return CHL_ERR_HIP;
+            const double ms = tk.stop();
+            if (phase != 1) { B.kernel_ms += ms; B.kernel_launches++; }
+        }
         (*launches)++;
         int32_t c32[4];
         unsigned long long c64[2];
@@ -238,7 +256,7 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         if (roots_host) {
             rest.insert(rest.end(), roots_host + next, roots_host + nroots);
         } else {
-            for (int32_t r = next; r < nroots; r++) rest.push_back(r);
+            for (int32_t r = next; r < nroots; r++) rest.push_back(root_base + r);
         }
         // grow by doubling: label counts per root fall steeply with rank, so
         // the roots seen so far do not predict the rest
@@ -451,6 +469,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.mode == CHL_MODE_PLAIN && o.wg_size == 1024) return CHL_ERR_INVALID_ARG;
     if (o.roots_in_flight < 0 || o.delta < 0) return CHL_ERR_INVALID_ARG;
     if (o.root_count < 0) return CHL_ERR_INVALID_ARG;
+    if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
     if (o.root_count > 0) {
         if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
         if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;
@@ -522,6 +541,108 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (A.oom) return CHL_ERR_OOM;
     if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
 
+    // ---- rank-prefix pruning (Section 4.3) in levels: the trees of roots
+    //      [0, 16) grow unpruned; then every level [g, 4g) is pruned by the
+    //      labels of the hubs [0, g), which are complete, and so on up to the
+    //      prefix size; the main phase is pruned by the whole prefix. The
+    //      labels found so far are regrouped by vertex after every level.
+    int launches = 0;
+    int prefix_launches = 0;
+    double prune_ms = 0;
+    int32_t grown = 0;
+    const double wm = 0.5 * (1.0 + B.maxw);
+    if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64) {
+        Timer tp(st);
+        const int32_t gmax = std::min<int32_t>(o.prune_hubs > 0 ? o.prune_hubs : MAX_PREFIX, n / 2);
+        int32_t* pcount = A.get<int32_t>(n);
+        int32_t* pfill = A.get<int32_t>(n);
+        int64_t* poff = A.get<int64_t>((size_t)n + 1);
+        if (A.oom) return CHL_ERR_OOM;
+        uint64_t* plab = nullptr;
+        size_t plab_cap = 0;
+        const int kpre = std::min(512, std::max(1, (int)(std::min<size_t>(4096, (size_t)(1ull << 33) / std::max<size_t>(1, slot_bytes(n, B.key_bits))))));
+        Slots s1{};
+        if (int r = alloc_slots(A, B, kpre, s1, st)) return r;
+        HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+        auto regroup = [&]() -> int {
+            unsigned long long used = 0;
+            HIPCHK(hipMemcpyAsync(&used, B.ctl64, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (used > plab_cap) {
+                if (plab) A.drop(plab);
+                plab_cap = std::max<size_t>(used, 2 * plab_cap);
+                plab = A.get<uint64_t>(plab_cap);
+                if (!plab) return CHL_ERR_OOM;
+            }
+            if (launch_prefix_labels(n, B.pool, used, pcount, poff, pfill, plab, scan_tmp, st)) return CHL_ERR_HIP;
+            B.poff = poff;
+            B.plab = plab;
+            B.cursor_base = used;
+            return 0;
+        };
+        // level 0
+        int32_t g = std::min<int32_t>(16, gmax);
+        // the first levels hold the largest trees: a full 1024-thread
+        // workgroup each
+        const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 8));
+        if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g, st, &launches, 2, 0)) return r;
+        if (int r = regroup()) return r;
+        grown = g;
+        bool keep = o.prune_hubs > 0 || !o.autotune;
+        if (!keep) {
+            // keep pruning only if the 16-hub prefix cuts the work of a
+            // rank-stratified sample of later trees at least in half (it does
+            // not on graphs whose top-ranked vertices cover few shortest
+            // paths, e.g. degree-ranked grids)
+            const int32_t p0 = std::min<int32_t>(gmax, n - 1), nprobe = std::min<int32_t>(128, n - p0);
+            std::vector<int32_t> probe;
+            for (int32_t i = 0; i < nprobe; i++) probe.push_back(p0 + (int32_t)((int64_t)(n - p0) * i / nprobe));
+            int64_t* sv = B.stats;
+            int64_t* tmp_stats = sv ? nullptr : A.get<int64_t>((size_t)n * STAT_COLS);
+            if (!sv && !tmp_stats) return CHL_ERR_OOM;
+            B.stats = sv ? sv : tmp_stats;
+            int64_t work[2] = {0, 0};
+            std::vector<int64_t> rows((size_t)n * STAT_COLS);
+            for (int on = 0; on < 2; on++) {
+                B.pbound = on ? g : 0;
+                HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+                if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, probe.data(), (int32_t)probe.size(), st,
+                                        &launches, 1))
+                    return r;
+                HIPCHK(hipMemcpy(rows.data(), B.stats, rows.size() * 8, hipMemcpyDeviceToHost));
+                for (int32_t r : probe) work[on] += rows[(size_t)r * STAT_COLS + 1];
+            }
+            // the probe roots' statistics rows are written again by the main phase
+            if (!sv) A.drop(tmp_stats);
+            B.stats = sv;
+            HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+            keep = 2 * work[1] < work[0];
+        }
+        B.pbound = 0;
+        if (keep) {
+            while (g < gmax) {
+                const int32_t g2 = std::min<int32_t>(gmax, 8 * g);
+                B.pbound = g;
+                if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g2 - g, st, &launches, 2, g))
+                    return r;
+                if (int r = regroup()) return r;
+                g = g2;
+            }
+            grown = g;
+            B.pbound = g;
+        }
+        free_slots(A, s1);
+        prefix_launches = launches;
+        B.grown = grown;
+        if (o.root_count > 0) {
+            // a root subset keeps only its own trees' labels
+            B.cursor_base = 0;
+            HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+            if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
+        }
+        prune_ms = tp.stop();
+    }
+
     // ---- parameters
     int k = 0, wg = 0;
     int64_t delta = 0;
@@ -531,12 +652,20 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     S.roots_in_flight = k;
     S.wg_size = wg;
     S.delta = delta;
+    S.prune_hubs = B.pbound;
+    S.prefix_roots = B.grown;
+    {
+        int dev = 0, khz = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess)
+            S.clock_khz = khz;
+    }
 
     // ---- trees
     Slots s{};
     if (int r = alloc_slots(A, B, o.mode == CHL_MODE_PLAIN ? 1 : k, s, st)) return r;
-    HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
-    int launches = 0;
+    HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
     Timer ttree(st);
     std::vector<int32_t> sel;
     if (o.root_count > 0)
@@ -544,10 +673,14 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     int r = o.mode == CHL_MODE_PLAIN
                 ? run_plain(A, B, s, wg, delta, o.early_term, sel, st, &launches)
                 : run_batched(A, B, s, wg, delta, o.early_term, sel.empty() ? nullptr : sel.data(),
-                              sel.empty() ? n : (int32_t)sel.size(), st, &launches);
+                              sel.empty() ? n - grown : (int32_t)sel.size(), st, &launches, 0,
+                              sel.empty() ? grown : 0);
     if (r) return r;
     S.tree_ms = ttree.stop();
-    S.launches = launches;
+    S.prefix_ms = prune_ms;
+    S.kernel_ms = B.kernel_ms;
+    S.kernel_launches = B.kernel_launches;
+    S.launches = launches - prefix_launches;
     free_slots(A, s);
     int32_t c32[4];
     unsigned long long used = 0;
@@ -618,7 +751,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta);
     if (!need) return 0;
-    TuneKey key{n, B.m, B.maxw, o.mode, graph_signature(g, st)};
+    TuneKey key{n, B.m, B.maxw, (o.mode * 8192 + B.grown) * 8192 + B.pbound, graph_signature(g, st)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -631,14 +764,20 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     // probe: the first roots (largest trees) and a rank-stratified sample
     std::vector<int32_t> probe;
-    // the head trees span the whole graph: fewer of them on large graphs
-    int32_t head = std::min<int32_t>(n, n > (1 << 18) ? 32 : 128);
-    for (int32_t r = 0; r < head; r++) probe.push_back(r);
-    int32_t strata = std::min<int32_t>(n - head, n > (1 << 18) ? 256 : 384);
-    for (int32_t i = 0; i < strata; i++) probe.push_back(head + (int32_t)((int64_t)(n - head) * i / strata));
+    // the head trees span the whole graph: fewer of them on large graphs;
+    // the trees of the common-label roots are done already
+    const int32_t r0 = B.grown;
+    int32_t head = std::min<int32_t>(n - r0, n > (1 << 18) ? 32 : 128);
+    for (int32_t r = 0; r < head; r++) probe.push_back(r0 + r);
+    int32_t strata = std::min<int32_t>(n - r0 - head, n > (1 << 18) ? 256 : 384);
+    for (int32_t i = 0; i < strata; i++)
+        probe.push_back(r0 + head + (int32_t)((int64_t)(n - r0 - head) * i / strata));
+    if (probe.empty()) return 0;
+    int64_t* saved_stats = B.stats;
+    B.stats = nullptr;              // probe runs leave no statistics
     auto t0 = std::chrono::steady_clock::now();
     double best = 1e30;
-    TuneVal bv{k, wg, delta};
+    TuneVal bv{k, wg, delta, B.pbound};
     int launches = 0;
     Slots s{};
     int kcur = 0;
@@ -652,14 +791,14 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             if (int r = alloc_slots(A, B, kk, s, st)) return r;
             kcur = kk;
         }
-        HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+        HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
         Timer t(st);
         if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st,
-                                &launches, true))
+                                &launches, 1))
             return r;
         double ms = t.stop();
         seen[{kk, w, d}] = ms;
-        if (ms < best) { best = ms; bv = TuneVal{kk, w, d}; }
+        if (ms < best) { best = ms; bv = TuneVal{kk, w, d, B.pbound}; }
         return 0;
     };
     // coordinate search: bucket width (coarse, then refined), workgroup
@@ -682,8 +821,8 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             if (int r = trial(kk, bv.wg, bv.delta)) return r;
     }
     free_slots(A, s);
-    HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
-    if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
+    B.stats = saved_stats;
+    HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     k = bv.k;

@@ -21,7 +21,7 @@ __global__ void k_count(const int32_t* __restrict__ pv, uint64_t total, const in
                         int32_t* __restrict__ count) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x)
-        atomicAdd(&count[order[pv[i]]], 1);
+        atomicAdd(&count[order ? order[pv[i]] : pv[i]], 1);
 }
 
 __global__ void k_scatter(const int32_t* __restrict__ pv, const int32_t* __restrict__ ph,
@@ -30,7 +30,7 @@ __global__ void k_scatter(const int32_t* __restrict__ pv, const int32_t* __restr
                           uint64_t* __restrict__ tmp) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        int32_t v = order[pv[i]];
+        int32_t v = order ? order[pv[i]] : pv[i];
         int64_t p = offsets[v] + atomicAdd(&fill[v], 1);
         tmp[p] = ((uint64_t)(uint32_t)ph[i] << 32) | (uint32_t)pd[i];
     }
@@ -69,6 +69,21 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
                            order, offsets, fill, tmp);
         if (launch_segsort_u64(tmp, offsets, n, (int64_t)total, sort_temp, st)) return -1;
         hipLaunchKernelGGL(k_split, dim3(g(total)), dim3(256), 0, st, tmp, total, hub_pos, dist);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
+                         int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, count, (int64_t)n);
+    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, fill, (int64_t)n);
+    if (used > 0)
+        hipLaunchKernelGGL(k_count, dim3(g(used)), dim3(256), 0, st, pool.v, used, (const int32_t*)nullptr, count);
+    if (launch_scan_i32_to_i64(count, offsets, n, scan_temp, st)) return -1;
+    if (used > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(g(used)), dim3(256), 0, st, pool.v, pool.hub, pool.dist, used,
+                           (const int32_t*)nullptr, offsets, fill, lab);
+        if (launch_segsort_u64(lab, offsets, n, (int64_t)used, nullptr, st)) return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

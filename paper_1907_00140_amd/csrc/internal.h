@@ -77,6 +77,14 @@ struct TreeParams {
     int32_t* failed;        // roots that could not emit (pool full)
     int32_t* nfailed;
     int32_t* far2;          // plain form: filtered far list, n entries
+    int32_t root_base;      // batched form without a root list: root = root_base + counter
+    // rank-prefix pruning: the labels found so far, by vertex (rank position)
+    // and sorted by hub, plab[poff[v] .. poff[v+1]) = (hub << 32) | dist;
+    // trees of roots >= pbound prune with the hubs [0, pbound) (their labels
+    // are complete); poff == NULL or pbound == 0 disables pruning
+    const int64_t* poff;
+    const uint64_t* plab;
+    int32_t pbound;
     // outputs
     int64_t* stats;         // [n][STAT_COLS] by root or NULL
     int32_t* err;
@@ -106,7 +114,8 @@ int launch_segsort_u64(uint64_t* keys, const int64_t* off, int64_t nseg, int64_t
                        void* temp, hipStream_t st);
 
 // tree.hip
-int launch_tree_batched(const TreeParams& p, int key_bits, int wg, bool probe, hipStream_t st);
+// phase: 0 main phase of a build, 1 autotuner probe, 2 common-label roots
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, int phase, hipStream_t st);
 int launch_tree_plain(const TreeParams& p, int key_bits, int wg, int grid, int32_t root,
                       int32_t* gstate, hipStream_t st);
 int plain_grid_size(int key_bits, int wg);
@@ -117,6 +126,12 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
                     int32_t* count, int64_t* offsets, int32_t* fill, uint64_t* tmp,
                     int32_t* hub_pos, int32_t* dist, void* scan_temp, void* sort_temp,
                     hipStream_t st);
+
+// assemble.hip: labels of the pool entries [0, used) grouped by vertex
+// (rank position) and sorted by hub, as (hub << 32) | dist words
+int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
+                         int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st);
+constexpr int MAX_PREFIX = 4096;   // largest pruning prefix (root distances live in LDS)
 
 // query.hip
 int launch_query(int32_t n, const int64_t* offsets, const int32_t* hub_pos, const int32_t* dist,

@@ -148,7 +148,8 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                                             int64_t T, int32_t* touched, int32_t* next,
                                             int32_t* far, C* cnt_touched, C* cnt_next,
                                             C* cnt_far, C* cnt_far_clean, unsigned long long* umax,
-                                            Expand<K, WG>& X, uint64_t& arcs) {
+                                            const int64_t* poff, const uint64_t* plab, uint32_t pbound,
+                                            const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -202,9 +203,36 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
             // Keys only decrease, so a value read earlier is never below the
             // current one: when the candidate is not below it, the atomic
             // would fail and is skipped.
+            bool cand = valid && nk < seen[j];
+            if (cand && dh) {
+                // Rank-prefix pruning (Section 4.3): the labels of the hubs
+                // [0, pbound), complete because their trees are done, give the
+                // length of the shortest root-u walk through each of them
+                // (dh holds the root's side). If one is no longer than the
+                // candidate, the candidate is either not a shortest path or a
+                // shortest path through a hub that outranks the root; either
+                // way it cannot lead to a label, and a vertex whose true key
+                // is clean never has such a hub on its shortest paths, so
+                // dropping the candidate changes no label. u's list is sorted
+                // by hub: read it 8 entries at a time, most important first.
+                const int64_t lb = poff[u], le = poff[u + 1];
+                bool more = true;
+                for (int64_t i = lb; i < le && cand && more; i += 8) {
+                    uint64_t lx[8];
+#pragma unroll
+                    for (int z = 0; z < 8; z++) lx[z] = i + z < le ? plab[i + z] : ~0ull;
+#pragma unroll
+                    for (int z = 0; z < 8; z++) {
+                        const uint32_t x = (uint32_t)(lx[z] >> 32);
+                        if (x >= pbound) { more = false; continue; }
+                        const uint32_t a = dh[x];
+                        if (a != 0xFFFFFFFFu && (uint64_t)a + (uint32_t)lx[z] <= nd) cand = false;
+                    }
+                }
+            }
             K old = seen[j];
-            if (valid && nk < seen[j]) old = amin<SCOPE>(&key[u], nk);
-            const bool imp = valid && nk < old;
+            if (cand) old = amin<SCOPE>(&key[u], nk);
+            const bool imp = cand && nk < old;
             const bool first = imp && old == KeyTraits<K>::INF;
             const bool tonear = imp && (int64_t)nd < T;
             bool pnear = false, pfar = false;
@@ -271,12 +299,15 @@ __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, con
     return cl == 0 && lb > S.umax;
 }
 
-// PROBE = 1 instantiates the same kernel under its own symbol for the
-// autotuner's probe runs, so profiles of complete builds see only them.
-template <typename K, int WG, int PROBE>
+// PHASE only names the launch (0: main phase of a build, 1: autotuner probe,
+// 2: the common-label roots grown before the main phase), so that profiles
+// separate them. PRUNE: rank-prefix pruning with p.poff / p.plab; the root's
+// distances to the prefix hubs live in dynamic LDS (p.pbound words).
+template <typename K, int WG, int PHASE, bool PRUNE>
 __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
     __shared__ BatchedLds<K, WG> S;
+    extern __shared__ uint32_t dh[];
     const int tid = threadIdx.x;
     const int64_t slot = blockIdx.x;
     K* key = (K*)p.s.key + slot * p.s.stride;
@@ -291,13 +322,23 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             int32_t r = -1;
             if (__hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
                 int32_t c = atomicAdd(p.next_root, 1);
-                if (c < p.nroots) r = p.roots ? p.roots[c] : c;
+                if (c < p.nroots) r = p.roots ? p.roots[c] : p.root_base + c;
             }
             S.root = r;
         }
         __syncthreads();
         const int32_t h = S.root;
         if (h < 0) break;
+        const bool prune = PRUNE && h >= p.pbound;
+        if (prune) {
+            for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
+            __syncthreads();
+            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
+                const uint64_t lx = p.plab[i];
+                const uint32_t x = (uint32_t)(lx >> 32);
+                if (x < (uint32_t)p.pbound) dh[x] = (uint32_t)lx;
+            }
+        }
 
         // ---- init: root key (0, clean) in near list 0
         if (tid == 0) {
@@ -335,7 +376,8 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                 for (int32_t base = 0; base < ncur; base += WG)
                     relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
-                                           &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, S.X, arcs);
+                                           &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, p.poff,
+                                           p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
@@ -518,7 +560,8 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
                                        (unsigned long long*)&gs[G_CNT0 + (it + 1) % 3],
                                        (unsigned long long*)&gs[G_FAR],
                                        (unsigned long long*)&gs[G_FARCLEAN],
-                                       (unsigned long long*)&gs[G_UMAX], S.X, arcs);
+                                       (unsigned long long*)&gs[G_UMAX], nullptr, nullptr, 0u, nullptr, S.X,
+                                       arcs);
             if (gtid == 0) { gs[G_CNT0 + (it + 2) % 3] = 0; gs[G_SETTLED] += ncur; }
             __threadfence();
             grid.sync();
@@ -627,11 +670,16 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
 }
 
 template <typename K, int WG>
-int launch_batched_t(const TreeParams& p, bool probe, hipStream_t st) {
-    if (probe)
-        hipLaunchKernelGGL((k_tree_batched<K, WG, 1>), dim3(p.s.k), dim3(WG), 0, st, p);
-    else
-        hipLaunchKernelGGL((k_tree_batched<K, WG, 0>), dim3(p.s.k), dim3(WG), 0, st, p);
+int launch_batched_t(const TreeParams& p, int phase, hipStream_t st) {
+    const bool pr = p.poff != nullptr && p.pbound > 0;
+    const size_t dl = pr ? (size_t)p.pbound * 4 : 0;
+    const dim3 g(p.s.k), b(WG);
+    if (phase == 1 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true>), g, b, dl, st, p);
+    else if (phase == 1) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, false>), g, b, 0, st, p);
+    else if (phase == 2 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, true>), g, b, dl, st, p);
+    else if (phase == 2) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, false>), g, b, 0, st, p);
+    else if (pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 0, true>), g, b, dl, st, p);
+    else hipLaunchKernelGGL((k_tree_batched<K, WG, 0, false>), g, b, 0, st, p);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -656,15 +704,15 @@ int plain_grid_t() {
 
 }  // namespace
 
-int launch_tree_batched(const TreeParams& p, int key_bits, int wg, bool probe, hipStream_t st) {
+int launch_tree_batched(const TreeParams& p, int key_bits, int wg, int phase, hipStream_t st) {
     if (key_bits == 32) {
-        if (wg == 256) return launch_batched_t<uint32_t, 256>(p, probe, st);
-        if (wg == 512) return launch_batched_t<uint32_t, 512>(p, probe, st);
-        if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, probe, st);
+        if (wg == 256) return launch_batched_t<uint32_t, 256>(p, phase, st);
+        if (wg == 512) return launch_batched_t<uint32_t, 512>(p, phase, st);
+        if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, phase, st);
     } else {
-        if (wg == 256) return launch_batched_t<uint64_t, 256>(p, probe, st);
-        if (wg == 512) return launch_batched_t<uint64_t, 512>(p, probe, st);
-        if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, probe, st);
+        if (wg == 256) return launch_batched_t<uint64_t, 256>(p, phase, st);
+        if (wg == 512) return launch_batched_t<uint64_t, 512>(p, phase, st);
+        if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, phase, st);
     }
     return -1;
 }

@@ -377,6 +377,21 @@ def check_sssp(lib, seed):
         assert np.array_equal(got, np.where(D[s] >= INF, -1, D[s]))
 
 
+def check_pruned(lib, n, m, wmax, seed):
+    """Pruned trees (Section 4.3) give the definition's labels."""
+    g = np.random.default_rng(seed)
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = csr_from_edges(n, e)
+    order = gg.random_rank(n, seed)
+    want = brute_labels(floyd_warshall(n, row, col, w), order)
+    for eta, grown in ((2, 2), (4, 6), (8, 8)):
+        lab = oracle.chl_pruned(row, col, w, order, eta, grown, threads=2, lib=lib)
+        assert oracle_labels(lab) == want, (eta, grown)
+    lab = oracle.chl_pruned(row, col, w, order, levels=[2, 6, 18], pmain=18, threads=2, lib=lib)
+    assert oracle_labels(lab) == want
+
+
 def run_all(lib):
     """Every pin, smallish; used against planted mistakes."""
     check_golden(lib, "fig1_example.txt")
@@ -393,3 +408,5 @@ def run_all(lib):
     check_sssp(lib, 7)
     for s in range(4):
         check_stats(lib, 20, 34, 2, 200 + s)
+    for s in range(4):
+        check_pruned(lib, 26, 44, 3, 300 + s)

@@ -56,7 +56,8 @@ def test_random_small(seed):
     _say("random_small", seed, n, m, wmax)
     ref = oracle.chl(row, col, w, order)
     for kw in (dict(mode="batched", delta=1 + seed % 4, roots_in_flight=1 + seed % 7, wg_size=256, autotune=False),
-               dict(mode="batched", delta=1000, wg_size=512, autotune=False),
+               dict(mode="batched", delta=1000, wg_size=512, autotune=False, prune_hubs=-1),
+               dict(mode="batched", delta=3, wg_size=1024, autotune=False, prune_hubs=4 * (1 + seed % 16)),
                dict(mode="plain", delta=2, autotune=False)):
         L, off, hub, dist = gpu_labels(row, col, w, order, **kw)
         assert_same_labels(off, hub, dist, ref, str(kw))
@@ -76,16 +77,19 @@ def test_grid64_full():
     assert np.array_equal(q, qref)
 
 
-@pytest.mark.parametrize("k,wg,delta", [(1, 256, 1), (3, 512, 7), (64, 1024, 50), (256, 256, 100),
-                                        (1024, 512, 400), (2048, 256, 10_000)])
-def test_parameter_invariance_rmat12(k, wg, delta):
-    """Every (roots in flight, workgroup size, bucket width) gives the same labels."""
+@pytest.mark.parametrize("k,wg,delta,eta", [(1, 256, 1, -1), (3, 512, 7, 16), (64, 1024, 50, 64),
+                                            (256, 256, 100, 4), (1024, 512, 400, 32), (2048, 256, 10_000, -1)])
+def test_parameter_invariance_rmat12(k, wg, delta, eta):
+    """Every (roots in flight, workgroup size, bucket width, pruning hubs)
+    gives the same labels."""
     c = gg.make_config("rmat12s9")
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
-    _say("invariance", k, wg, delta)
+    _say("invariance", k, wg, delta, eta)
     L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], mode="batched",
-                                   roots_in_flight=k, wg_size=wg, delta=delta, autotune=False)
+                                   roots_in_flight=k, wg_size=wg, delta=delta, autotune=False, prune_hubs=eta if eta < 0 else 4 * (eta // 4 or 1))
     assert_same_labels(off, hub, dist, ref)
+    st = L.stats(per_root=True)
+    assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
 
 
 def test_repeatable_rmat14():
@@ -113,6 +117,9 @@ def test_rmat16_full():
     st = L.stats(per_root=True)
     assert st["labels"] == ref.total
     assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])   # labels per root
+    _say("rmat16 gpu, no pruning")
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], prune_hubs=-1)
+    assert_same_labels(off, hub, dist, ref)
 
 
 def test_invalid_inputs():

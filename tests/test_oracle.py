@@ -116,3 +116,51 @@ def test_queries_match_dijkstra_grid64(lib):
 @pytest.mark.parametrize("seed", range(12))
 def test_work_counts(lib, seed):
     pins.check_stats(lib, 18 + seed, 30 + 2 * seed, 1 + seed % 3, 300 + seed)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_pruned_equals_definition(lib, seed):
+    """Rank-prefix pruning (Section 4.3) leaves every label unchanged:
+    brute force on random tie-heavy multigraphs, several prefix sizes."""
+    g = np.random.default_rng(seed)
+    n = 20 + seed * 3
+    m = int(n * 1.8)
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, 2 + seed % 4, m))]
+    row, col, w = pins.csr_from_edges(n, e)
+    order = gg.random_rank(n, seed) if seed % 2 else gg.degree_rank(row, seed)
+    want = pins.brute_labels(pins.floyd_warshall(n, row, col, w), order)
+    for eta, grown in ((1, 1), (4, 4), (4, 9), (8, 8), (n, n)):
+        lab = oracle.chl_pruned(row, col, w, order, eta, grown, threads=2, lib=lib)
+        assert pins.oracle_labels(lab) == want, (eta, grown)
+
+
+def test_pruned_work_grid64_rmat12(lib):
+    """Same labels as the unpruned trees on larger graphs, with less work."""
+    for name in ("grid64", "rmat12s9"):
+        c = gg.make_config(name)
+        ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], lib=lib)
+        for eta, grown in ((16, 16), (16, 64), (64, 64)):
+            lab = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], eta, grown, lib=lib)
+            assert np.array_equal(lab.offsets, ref.offsets)
+            assert np.array_equal(lab.hub_pos, ref.hub_pos)
+            assert np.array_equal(lab.dist, ref.dist)
+            assert np.array_equal(lab.stats[:, 2], ref.stats[:, 2])
+            assert lab.stats[:, 1].sum() <= ref.stats[:, 1].sum()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_levels_equal_definition(lib, seed):
+    """Pruning in levels (each level pruned by the complete prefix below it)
+    leaves every label unchanged."""
+    g = np.random.default_rng(100 + seed)
+    n = 30 + seed * 4
+    m = int(n * 2)
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, 2 + seed % 3, m))]
+    row, col, w = pins.csr_from_edges(n, e)
+    order = gg.degree_rank(row, seed)
+    want = pins.brute_labels(pins.floyd_warshall(n, row, col, w), order)
+    for levels, pmain in (([2, 8], 8), ([1, 4, 16], 16), ([3, 9, 27], 9), ([4, 16], 0)):
+        lab = oracle.chl_pruned(row, col, w, order, levels=levels, pmain=pmain, threads=2, lib=lib)
+        assert pins.oracle_labels(lab) == want, (levels, pmain)

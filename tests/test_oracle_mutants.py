@@ -36,6 +36,10 @@ MUTANTS = {
     "query_skip": ("if (hub[i] < hub[j]) i++;", "if (hub[i] < hub[j]) j++;"),
     # sparse reset forgets the ancestor array
     "reset_anc": ("w->dist[v] = INF64; w->anc[v] = v;", "w->dist[v] = INF64;"),
+    # pruning threshold one too high: drops shortest clean candidates
+    "prune_threshold": ("prefix_query(P, h, u) <= nd) continue;", "prefix_query(P, h, u) <= nd + 1) continue;"),
+    # prefix label distances one too small: over-pruning
+    "prefix_dist": ("P->dist[k] = ld[t][i];", "P->dist[k] = ld[t][i] - 1;"),
     # sssp: wrong weight index
     "sssp_w": ("int64_t nd = it.d + wt[e];\n            if (nd < out[col[e]])",
                "int64_t nd = it.d + wt[row_ptr[it.v]];\n            if (nd < out[col[e]])"),
