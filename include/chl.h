@@ -123,8 +123,16 @@ typedef struct chl_build_opts {
                                 prefix hub is no longer. Same labels either
                                 way. > 0: that prefix size; 0: 4096, kept only
                                 if the 16-hub level speeds up a probe of later
-                                trees (always kept when autotune is 0); < 0:
+                                trees (decided once per graph and ranking and
+                                cached; always kept when autotune is 0); < 0:
                                 off. Ignored by the plain form. */
+    int32_t team_wgs;        /* batched form: workgroups per tree for the levels
+                                of rank-prefix pruning that hold fewer trees than
+                                the device holds workgroups (the first, largest
+                                trees). 0: chosen from the device size; 1: one
+                                workgroup per tree; 2..16: that many, capped so
+                                that every team of a launch is resident (a
+                                cooperative launch). Same labels either way. */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */

@@ -115,6 +115,7 @@ struct TuneVal {
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
+std::map<TuneKey, bool> g_prune_keep;   // outcome of the pruning probe
 
 // Device state shared by one build.
 struct Build {
@@ -140,6 +141,7 @@ struct Build {
     int32_t grown = 0;                   // roots [0, grown) done before the main phase
     double kernel_ms = 0;                // event-timed production tree launches
     int64_t kernel_launches = 0;
+    uint64_t sig = 0;                    // graph and ranking signature (tuning caches)
 };
 
 size_t slot_bytes(int32_t n, int key_bits) {
@@ -214,11 +216,21 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     return p;
 }
 
-// Run the batched kernel over roots (NULL = all, in rank order) until every
-// root has emitted, growing the pool when it fills up.
+// Teams of workgroups (one tree per team at a time) for a launch over few
+// large trees; the team slots are the first nteams slots of the Slots passed.
+struct TeamCfg {
+    int size = 0;              // workgroups per team
+    int nteams = 0;
+    long long* tstate = nullptr;  // [nteams][TEAM_WORDS]
+    int32_t* far2 = nullptr;      // [nteams][n]
+};
+
+// Run the batched kernel (or the team kernel when team is set) over roots
+// (NULL = all, in rank order) until every root has emitted, growing the pool
+// when it fills up.
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
                 const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
-                int phase = 0, int32_t root_base = 0) {
+                int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr) {
     std::vector<int32_t> pending;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
@@ -231,7 +243,13 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         TreeParams p = params(B, s, delta, early, dev_roots, nroots, root_base);
         {
             Timer tk(st);
-            if (launch_tree_batched(p, B.key_bits, wg, phase, st)) return CHL_ERR_HIP;
+            if (team) {
+                HIPCHK(hipMemsetAsync(team->tstate, 0, (size_t)team->nteams * TEAM_WORDS * 8, st));
+                if (launch_tree_team(p, B.key_bits, wg, team->size, team->nteams, team->tstate, team->far2, st))
+                    return CHL_ERR_HIP;
+            } else if (launch_tree_batched(p, B.key_bits, wg, phase, st)) {
+                return CHL_ERR_HIP;
+            }
             const double ms = tk.stop();
             if (phase != 1) { B.kernel_ms += ms; B.kernel_launches++; }
         }
@@ -242,6 +260,7 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         HIPCHK(hipMemcpyAsync(c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
+        if (c32[3] & ERR_BIT_TEAM) return CHL_ERR_HIP;
         if (!(c32[3] & ERR_BIT_POOL)) break;
         // pool full: keep what fitted, then resume with the failed roots and
         // the roots the queue had not handed out yet
@@ -319,24 +338,29 @@ int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int ear
     return 0;
 }
 
-uint64_t graph_signature(const chl_graph* g, hipStream_t st) {
-    // a few row offsets and arcs sampled at fixed positions
+uint64_t graph_signature(const chl_graph* g, const int32_t* order, hipStream_t st) {
+    // a few row offsets, arcs and ranking entries sampled at fixed positions
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
     mix((uint64_t)g->n);
     mix((uint64_t)g->n_arcs);
+    int64_t r[16] = {};
+    int32_t c[16] = {}, w[16] = {}, rk[16] = {};
     for (int i = 0; i < 16; i++) {
-        int64_t v = (int64_t)g->n * i / 16, r = 0;
-        int64_t e = g->n_arcs ? g->n_arcs * i / 16 : 0;
-        int32_t c = 0, w = 0;
-        (void)hipMemcpyAsync(&r, g->row_ptr + v, 8, hipMemcpyDeviceToHost, st);
+        const int64_t v = (int64_t)g->n * i / 16;
+        const int64_t e = g->n_arcs ? g->n_arcs * i / 16 : 0;
+        (void)hipMemcpyAsync(&r[i], g->row_ptr + v, 8, hipMemcpyDeviceToHost, st);
+        (void)hipMemcpyAsync(&rk[i], order + v, 4, hipMemcpyDeviceToHost, st);
         if (g->n_arcs) {
-            (void)hipMemcpyAsync(&c, g->col + e, 4, hipMemcpyDeviceToHost, st);
-            (void)hipMemcpyAsync(&w, g->w + e, 4, hipMemcpyDeviceToHost, st);
+            (void)hipMemcpyAsync(&c[i], g->col + e, 4, hipMemcpyDeviceToHost, st);
+            (void)hipMemcpyAsync(&w[i], g->w + e, 4, hipMemcpyDeviceToHost, st);
         }
-        (void)hipStreamSynchronize(st);
-        mix((uint64_t)r);
-        mix((uint64_t)(uint32_t)c << 32 | (uint32_t)w);
+    }
+    (void)hipStreamSynchronize(st);
+    for (int i = 0; i < 16; i++) {
+        mix((uint64_t)r[i]);
+        mix((uint64_t)(uint32_t)c[i] << 32 | (uint32_t)w[i]);
+        mix((uint64_t)(uint32_t)rk[i]);
     }
     return h;
 }
@@ -470,6 +494,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.roots_in_flight < 0 || o.delta < 0) return CHL_ERR_INVALID_ARG;
     if (o.root_count < 0) return CHL_ERR_INVALID_ARG;
     if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
+    if (o.team_wgs < 0 || o.team_wgs > 16) return CHL_ERR_INVALID_ARG;
     if (o.root_count > 0) {
         if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
         if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;
@@ -522,6 +547,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     A.drop(cnt);
     S.prep_ms = tprep.stop();
     B.g = RGraph{n, B.m, rrow, rarc};
+    B.sig = graph_signature(g, order, st);
     // 32-bit keys are exact when no simple path can reach 2^31 - 1
     B.key_bits = ((double)(n - 1) * (double)B.maxw <= 2147483646.0) ? 32 : 64;
     S.key_bits = B.key_bits;
@@ -583,13 +609,50 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         // level 0
         int32_t g = std::min<int32_t>(16, gmax);
         // the first levels hold the largest trees: a full 1024-thread
-        // workgroup each
+        // workgroup each. The unpruned trees of level 0 span the graph and
+        // run fastest with narrow buckets (little re-relaxation); pruned
+        // trees are small and latency bound, so wide buckets (fewer rounds)
+        // serve them better (measured on R-MAT scales 16 and 20)
         const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 8));
-        if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g, st, &launches, 2, 0)) return r;
+        const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
+        // levels with fewer trees than the device holds 1024-thread
+        // workgroups run as teams of workgroups, one tree per team
+        const int tcap = o.team_wgs == 1 ? 0 : team_capacity(B.key_bits, 1024);
+        auto team_shape = [&](int32_t nr, TeamCfg& tc) -> bool {
+            if (tcap < 2 || nr <= 0 || 2 * nr > tcap) return false;
+            tc.size = std::min(o.team_wgs ? o.team_wgs : 16, tcap / nr);
+            tc.nteams = std::min<int>(std::min<int>(nr, tcap / std::max(1, tc.size)), s1.k);
+            return tc.size >= 2;
+        };
+        int tmax = 0;
+        for (int32_t a = 0, b = g; a < gmax; a = b, b = std::min<int32_t>(gmax, 8 * b)) {
+            TeamCfg tc;
+            if (team_shape(b - a, tc)) tmax = std::max(tmax, tc.nteams);
+        }
+        int32_t* tfar2 = tmax ? A.get<int32_t>((size_t)tmax * n) : nullptr;
+        long long* tstate = tmax ? A.get<long long>((size_t)tmax * TEAM_WORDS) : nullptr;
+        if (A.oom) return CHL_ERR_OOM;
+        auto team_for = [&](int32_t nr, TeamCfg& tc) -> const TeamCfg* {
+            if (!team_shape(nr, tc) || tc.nteams > tmax) return nullptr;
+            tc.far2 = tfar2;
+            tc.tstate = tstate;
+            return &tc;
+        };
+        TeamCfg tc0;
+        if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
+                                team_for(g, tc0)))
+            return r;
         if (int r = regroup()) return r;
         grown = g;
+        bool probed = false;
         bool keep = o.prune_hubs > 0 || !o.autotune;
+        const TuneKey pkey{n, B.m, B.maxw, -1, B.sig};
         if (!keep) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_prune_keep.find(pkey);
+            if (it != g_prune_keep.end()) keep = it->second, probed = true;
+        }
+        if (!keep && !probed) {
             // keep pruning only if the 16-hub prefix cuts the work of a
             // rank-stratified sample of later trees at least in half (it does
             // not on graphs whose top-ranked vertices cover few shortest
@@ -617,13 +680,17 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             B.stats = sv;
             HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
             keep = 2 * work[1] < work[0];
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_prune_keep[pkey] = keep;
         }
         B.pbound = 0;
         if (keep) {
             while (g < gmax) {
                 const int32_t g2 = std::min<int32_t>(gmax, 8 * g);
                 B.pbound = g;
-                if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g2 - g, st, &launches, 2, g))
+                TeamCfg tc;
+                if (int r = run_batched(A, B, s1, 1024, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
+                                        team_for(g2 - g, tc)))
                     return r;
                 if (int r = regroup()) return r;
                 g = g2;
@@ -632,6 +699,8 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             B.pbound = g;
         }
         free_slots(A, s1);
+        if (tfar2) A.drop(tfar2);
+        if (tstate) A.drop(tstate);
         prefix_launches = launches;
         B.grown = grown;
         if (o.root_count > 0) {
@@ -751,7 +820,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta);
     if (!need) return 0;
-    TuneKey key{n, B.m, B.maxw, (o.mode * 8192 + B.grown) * 8192 + B.pbound, graph_signature(g, st)};
+    TuneKey key{n, B.m, B.maxw, (o.mode * 8192 + B.grown) * 8192 + B.pbound, B.sig};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);

@@ -30,6 +30,7 @@ enum : int32_t {
     ERR_BIT_OVERFLOW = 1,     // a label distance >= 2^31 - 1
     ERR_BIT_INVALID = 2,      // invalid input detected on the device
     ERR_BIT_POOL = 4,         // label pool full (host grows it and resumes)
+    ERR_BIT_TEAM = 8,         // a team barrier wait exceeded its bound (team aborted)
 };
 
 // Graph after rank renumbering: vertex id = rank position, so "u outranks
@@ -120,6 +121,14 @@ int launch_tree_plain(const TreeParams& p, int key_bits, int wg, int grid, int32
                       int32_t* gstate, hipStream_t st);
 int plain_grid_size(int key_bits, int wg);
 size_t plain_gstate_words();
+// Teams: nteams teams of team_size workgroups each grow the trees of the
+// root queue, one tree per team at a time (cooperative launch). Team slot i
+// is s.key/flags/touched/lists slot i plus far2[i * n]; tstate holds
+// TEAM_WORDS int64 words per team, zeroed before the launch.
+constexpr int TEAM_WORDS = 32;
+int launch_tree_team(const TreeParams& p, int key_bits, int wg, int team_size, int nteams,
+                     long long* tstate, int32_t* far2, hipStream_t st);
+int team_capacity(int key_bits, int wg);   // co-resident workgroups of the team kernel
 
 // assemble.hip
 int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t total,

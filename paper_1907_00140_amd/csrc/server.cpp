@@ -154,6 +154,9 @@ void chl_server::run_build(size_t idx, int slot) {
         bo.wg_size = 256;
         bo.autotune = 0;
         bo.stats = 0;
+        // builds share the device with queries and other builds: no
+        // cooperative (whole-team resident) launches
+        bo.team_wgs = 1;
         code = chl_build(&g, d_order, &bo, &al, (void*)s, &L);
     }
     for (void* p : {(void*)d_row, (void*)d_col, (void*)d_w, (void*)d_order})

@@ -76,6 +76,20 @@ __device__ __forceinline__ uint32_t aand(uint32_t* p, uint32_t v) { return __hip
 
 __device__ __forceinline__ uint32_t fshift(int32_t v) { return (uint32_t)(v & 7) * 4u; }
 
+// Entries of the vertex lists (near, far, touched) are read and written with
+// relaxed atomics at the scope of the workgroups that share the tree: plain
+// accesses in the batched form (workgroup scope), device-coherent ones when a
+// team of workgroups shares it, so that a team barrier needs no cache
+// write-back. A vertex id read from a list is clamped into [0, n): it always
+// is in range; the clamp only guarantees that no access can leave the arrays.
+template <int SCOPE>
+__device__ __forceinline__ int32_t lget(const int32_t* p, int32_t n) {
+    const uint32_t v = (uint32_t)__hip_atomic_load(const_cast<int32_t*>(p), __ATOMIC_RELAXED, SCOPE);
+    return (int32_t)(v < (uint32_t)n ? v : (uint32_t)(n - 1));
+}
+template <int SCOPE>
+__device__ __forceinline__ void lput(int32_t* p, int32_t v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, SCOPE); }
+
 // Block-wide exclusive scan of uint32 (WG threads). wsum: WG/64 entries of LDS.
 template <int WG>
 __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* wsum, uint32_t& total) {
@@ -153,7 +167,7 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
-        int32_t v = cur[base + tid];
+        int32_t v = lget<SCOPE>(&cur[base + tid], g.n);
         aand<SCOPE>(&flags[v >> 3], ~(curbit << fshift(v)));
         K kv = ld<SCOPE>(&key[v]);
         int64_t b = g.row[v];
@@ -245,11 +259,11 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                 pfar = fresh && !tonear;
             }
             int64_t q = wave_append(first, cnt_touched);
-            if (first) touched[q] = u;
+            if (first && q < g.n) lput<SCOPE>(&touched[q], u);
             q = wave_append(pnear, cnt_next);
-            if (pnear) next[q] = u;
+            if (pnear && q < g.n) lput<SCOPE>(&next[q], u);
             q = wave_append(pfar, cnt_far);
-            if (pfar) far[q] = u;
+            if (pfar && q < g.n) lput<SCOPE>(&far[q], u);
             const bool pfc = pfar && (nk & 1);
             (void)wave_append(pfc, cnt_far_clean);
         }
@@ -669,6 +683,298 @@ __global__ __launch_bounds__(WG) void k_tree_plain(TreeParams p, int32_t h, long
     }
 }
 
+// ---------------------------------------------------------------- teams
+// A team of W workgroups grows one tree at a time: the rounds of the plain
+// form confined to W workgroups, with the rank-ordered root queue of the
+// batched form over the teams. It serves the first trees of a build, which
+// span most of the graph and are too few to fill the device with one
+// workgroup each. The team's words (int64, zero at launch):
+enum {
+    T_CNT0 = 0, T_CNT1, T_CNT2,   // near list counts, rotating by round % 3
+    T_FAR, T_FAR2, T_TOUCHED,     // far list, filtered far list, touched list
+    T_MIN, T_CLEAN, T_T,          // bucket-end filter results, bucket bound
+    T_SETTLED, T_ARCS, T_NLAB, T_BASE, T_FILL, T_FARCLEAN, T_UMAX,
+    T_ROOT,
+    T_SMIN0, T_SMIN1, T_SCL0, T_SCL1,   // round-level stop test, by round parity
+    T_BAR, T_ABORT,
+    T_WORDS_USED
+};
+static_assert(T_WORDS_USED <= TEAM_WORDS, "team words");
+
+// Polls of a barrier counter before the team gives up (seconds; a barrier
+// normally completes within microseconds).
+constexpr int TEAM_SPIN_LIMIT = 1 << 22;
+
+template <typename K, int WG>
+struct TeamLds {
+    Expand<K, WG> X;
+    unsigned long long red64[WG / 64];
+    int ok;
+};
+
+template <typename T>
+__device__ __forceinline__ T twl(long long* tw, int i) {
+    return (T)__hip_atomic_load(&tw[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void tws(long long* tw, int i, long long v) {
+    __hip_atomic_store(&tw[i], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Barrier of the W workgroups of a team. Everything the workgroups of a team
+// share (keys, flags, list entries, team words) is accessed with
+// device-coherent atomics, so a barrier needs no cache write-back or
+// invalidation: every wave waits until its own memory operations have
+// completed, then the first thread of the workgroup adds one arrival to the
+// team counter and waits until it reaches nb * W, nb being the number of team
+// barriers so far (the same in every workgroup of the team, which all run the
+// same sequence of barriers). Returns false when the team is aborted: a wait
+// that exceeded TEAM_SPIN_LIMIT polls, here or in another workgroup of the
+// team.
+template <typename L>
+__device__ __forceinline__ bool team_sync(long long* tw, int W, unsigned long long& nb, L& S, int32_t* err) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    nb++;
+    if (threadIdx.x == 0) {
+        unsigned long long* bar = (unsigned long long*)&tw[T_BAR];
+        int ok = 1;
+        atomicAdd(bar, 1ull);
+        const unsigned long long target = nb * (unsigned long long)W;
+        for (int spins = 0;
+             __hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; spins++) {
+            if (spins > TEAM_SPIN_LIMIT || twl<long long>(tw, T_ABORT) != 0) {
+                ok = 0;
+                tws(tw, T_ABORT, 1);
+                atomicOr(err, ERR_BIT_TEAM);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        S.ok = ok;
+    }
+    __syncthreads();
+    return S.ok != 0;
+}
+
+template <typename K, int WG, bool PRUNE>
+__global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long* tstate, int32_t* far2_all) {
+    constexpr int SC = __HIP_MEMORY_SCOPE_AGENT;
+    typedef unsigned long long ull;
+    __shared__ TeamLds<K, WG> S;
+    extern __shared__ uint32_t dh[];
+    const int tid = threadIdx.x;
+    const int team = blockIdx.x / W, trank = blockIdx.x % W;
+    const int64_t tgtid = (int64_t)trank * WG + tid, tthreads = (int64_t)W * WG;
+    const bool leader = trank == 0 && tid == 0;
+    long long* tw = tstate + (int64_t)team * TEAM_WORDS;
+    K* key = (K*)p.s.key + team * p.s.stride;
+    uint32_t* flags = p.s.flags + team * p.s.fstride;
+    int32_t* touched = p.s.touched + team * p.s.stride;
+    int32_t* lists = p.s.lists + team * 3 * p.s.stride;
+    int32_t* far = lists + 2 * p.s.stride;
+    int32_t* far2 = far2_all + team * p.s.stride;
+    const int32_t n = p.g.n;
+    const int64_t delta = p.delta;
+    const long long INF = 0x7FFFFFFFFFFFFFFFll;
+    ull nb = 0;
+    uint64_t t_start = 0;
+
+    for (;;) {
+        // ---- the team leader takes the next root and sets up its tree
+        if (leader) {
+            int32_t r = -1;
+            if (ld<SC>(p.stop) == 0) {
+                int32_t c = atomicAdd(p.next_root, 1);
+                if (c < p.nroots) r = p.roots ? p.roots[c] : p.root_base + c;
+            }
+            if (r >= 0) {
+                for (int i = 0; i < T_ROOT; i++) tws(tw, i, 0);
+                tws(tw, T_CNT0, 1);
+                tws(tw, T_TOUCHED, 1);
+                tws(tw, T_MIN, INF);
+                tws(tw, T_T, delta);
+                tws(tw, T_SMIN0, INF); tws(tw, T_SMIN1, INF);
+                tws(tw, T_SCL0, 0); tws(tw, T_SCL1, 0);
+                st<SC>(&key[r], pack<K>(0, 1));
+                lput<SC>(&touched[0], r);
+                lput<SC>(&lists[0], r);
+                aor<SC>(&flags[r >> 3], 1u << fshift(r));
+                t_start = __builtin_amdgcn_s_memrealtime();
+            }
+            tws(tw, T_ROOT, r);
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        const int32_t h = twl<int32_t>(tw, T_ROOT);
+        if (h < 0) return;
+        const bool prune = PRUNE && h >= p.pbound;
+        if (prune) {
+            for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
+            __syncthreads();
+            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
+                const uint64_t lx = p.plab[i];
+                const uint32_t x = (uint32_t)(lx >> 32);
+                if (x < (uint32_t)p.pbound) dh[x] = (uint32_t)lx;
+            }
+            __syncthreads();
+        }
+        int it = 0;
+        bool early = false;
+        uint64_t arcs = 0;
+        for (;;) {
+            // words of the next round's stop test start clean
+            if (leader) { tws(tw, T_SMIN0 + ((it + 1) & 1), INF); tws(tw, T_SCL0 + ((it + 1) & 1), 0); }
+            const int64_t T = twl<int64_t>(tw, T_T);
+            const int32_t ncur = min(twl<int32_t>(tw, T_CNT0 + it % 3), n);
+            const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
+            int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
+            int32_t* next = lists + (int64_t)((it + 1) & 1) * p.s.stride;
+            if (ncur > 0) {
+                // ---- early termination between rounds (the test of the
+                //      batched form, over the whole team)
+                if (p.early_term && twl<long long>(tw, T_FARCLEAN) == 0) {
+                    ull mn = ~0ull, cl = 0;
+                    for (int64_t i = tgtid; i < ncur; i += tthreads) {
+                        const K kv = ld<SC>(&key[lget<SC>(&cur[i], n)]);
+                        const ull d = (ull)(kv >> 1);
+                        mn = d < mn ? d : mn;
+                        cl |= (ull)(kv & 1);
+                    }
+                    mn = block_reduce<WG>(mn, S.red64, ~0ull, [](ull a, ull b) { return a < b ? a : b; });
+                    cl = block_reduce<WG>(cl, S.red64, 0ull, [](ull a, ull b) { return a | b; });
+                    if (tid == 0) {
+                        if (mn != ~0ull) atomicMin((ull*)&tw[T_SMIN0 + (it & 1)], mn);
+                        if (cl) atomicOr((ull*)&tw[T_SCL0 + (it & 1)], cl);
+                    }
+                    if (!team_sync(tw, W, nb, S, p.err)) return;
+                    const ull smin = twl<ull>(tw, T_SMIN0 + (it & 1));
+                    const ull lb = smin < (ull)T ? smin : (ull)T;
+                    if (twl<ull>(tw, T_SCL0 + (it & 1)) == 0 && lb > twl<ull>(tw, T_UMAX)) {
+                        const int32_t nfar = min(twl<int32_t>(tw, T_FAR), n);
+                        for (int64_t i = tgtid; i < ncur; i += tthreads) {
+                            const int32_t v = lget<SC>(&cur[i], n);
+                            aand<SC>(&flags[v >> 3], ~(curbit << fshift(v)));
+                        }
+                        for (int64_t i = tgtid; i < nfar; i += tthreads) {
+                            const int32_t v = lget<SC>(&far[i], n);
+                            aand<SC>(&flags[v >> 3], ~(FAR_BIT << fshift(v)));
+                        }
+                        early = true;
+                        break;
+                    }
+                }
+                for (int32_t base = trank * WG; base < ncur; base += W * WG)
+                    relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
+                                           nextbit, h, T, touched, next, far, (ull*)&tw[T_TOUCHED],
+                                           (ull*)&tw[T_CNT0 + (it + 1) % 3], (ull*)&tw[T_FAR],
+                                           (ull*)&tw[T_FARCLEAN], (ull*)&tw[T_UMAX], p.poff, p.plab,
+                                           (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs);
+                if (leader) {
+                    tws(tw, T_CNT0 + (it + 2) % 3, 0);
+                    tws(tw, T_SETTLED, twl<long long>(tw, T_SETTLED) + ncur);
+                }
+                if (!team_sync(tw, W, nb, S, p.err)) return;
+                it++;
+                continue;
+            }
+            // ---- bucket done: filter far into far2 (drop settled entries)
+            const int32_t nfar = min(twl<int32_t>(tw, T_FAR), n);
+            ull mymin = ~0ull, myclean = 0;
+            for (int64_t i = tgtid; i < nfar; i += tthreads) {
+                const int32_t v = lget<SC>(&far[i], n);
+                aand<SC>(&flags[v >> 3], ~(FAR_BIT << fshift(v)));
+                const K kv = ld<SC>(&key[v]);
+                const bool keep = (int64_t)(kv >> 1) >= T;
+                if (keep) {
+                    mymin = min(mymin, (ull)(kv >> 1));
+                    myclean += (ull)(kv & 1);
+                }
+                const int64_t q = wave_append(keep, (ull*)&tw[T_FAR2]);
+                if (keep && q < n) lput<SC>(&far2[q], v);
+            }
+            mymin = block_reduce<WG>(mymin, S.red64, ~0ull, [](ull a, ull b) { return a < b ? a : b; });
+            myclean = block_reduce<WG>(myclean, S.red64, 0ull, [](ull a, ull b) { return a + b; });
+            if (tid == 0) {
+                if (mymin != ~0ull) atomicMin((ull*)&tw[T_MIN], mymin);
+                if (myclean) atomicAdd((ull*)&tw[T_CLEAN], myclean);
+            }
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+            const int32_t nkeep = min(twl<int32_t>(tw, T_FAR2), n);
+            const bool done = nkeep == 0 || (p.early_term && twl<long long>(tw, T_CLEAN) == 0);
+            const int64_t Tn = done ? 0 : (twl<int64_t>(tw, T_MIN) / delta + 1) * delta;
+            if (!team_sync(tw, W, nb, S, p.err)) return;   // everyone has read the results
+            if (done) { early = nkeep > 0; break; }
+            if (leader) {
+                tws(tw, T_FAR, 0); tws(tw, T_FAR2, 0); tws(tw, T_CLEAN, 0); tws(tw, T_MIN, INF);
+                tws(tw, T_T, Tn); tws(tw, T_FARCLEAN, 0);
+            }
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+            // ---- next bucket: far2 -> near list of this round, or back to far
+            int32_t* ncurl = lists + (int64_t)(it & 1) * p.s.stride;
+            for (int64_t i = tgtid; i < nkeep; i += tthreads) {
+                const int32_t v = lget<SC>(&far2[i], n);
+                const K kv = ld<SC>(&key[v]);
+                const bool tonear = (int64_t)(kv >> 1) < Tn;
+                int64_t q = wave_append(tonear, (ull*)&tw[T_CNT0 + it % 3]);
+                if (tonear && q < n) { lput<SC>(&ncurl[q], v); aor<SC>(&flags[v >> 3], curbit << fshift(v)); }
+                q = wave_append(!tonear, (ull*)&tw[T_FAR]);
+                if (!tonear && q < n) { lput<SC>(&far[q], v); aor<SC>(&flags[v >> 3], FAR_BIT << fshift(v)); }
+                (void)wave_append(!tonear && (kv & 1), (ull*)&tw[T_FARCLEAN]);
+            }
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+        }
+        // ---- emit the labels of clean vertices, reset the slot
+        const int64_t nt = min(twl<int64_t>(tw, T_TOUCHED), (int64_t)n);
+        ull mycnt = 0;
+        for (int64_t i = tgtid; i < nt; i += tthreads) mycnt += (ull)(ld<SC>(&key[lget<SC>(&touched[i], n)]) & 1);
+        mycnt = block_reduce<WG>(mycnt, S.red64, 0ull, [](ull a, ull b) { return a + b; });
+        if (tid == 0) {
+            atomicAdd((ull*)&tw[T_NLAB], mycnt);
+            atomicAdd((ull*)&tw[T_ARCS], (ull)arcs);
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        if (leader) {
+            const ull nl = twl<ull>(tw, T_NLAB);
+            const ull b = atomicAdd(p.pool.cursor, nl);
+            if (b + nl > p.pool.cap) {
+                tws(tw, T_BASE, -1);
+                atomicOr(p.err, ERR_BIT_POOL);
+                atomicExch(p.stop, 1);
+                atomicMin(p.pool.fail_base, b);
+                p.failed[atomicAdd(p.nfailed, 1)] = h;
+            } else {
+                tws(tw, T_BASE, (long long)b);
+            }
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        const long long pb = twl<long long>(tw, T_BASE);
+        const long long nl = twl<long long>(tw, T_NLAB);
+        bool ovf = false;
+        for (int64_t i = tgtid; i < nt; i += tthreads) {
+            const int32_t v = lget<SC>(&touched[i], n);
+            const K kv = ld<SC>(&key[v]);
+            const bool lab = (kv & 1) != 0;
+            const uint64_t d = (uint64_t)(kv >> 1);
+            st<SC>(&key[v], KeyTraits<K>::INF);
+            const int64_t q = wave_append(lab, (ull*)&tw[T_FILL]);
+            if (lab && pb >= 0 && q < nl) {
+                ovf |= d > 0x7FFFFFFEull;
+                p.pool.v[pb + q] = v;
+                p.pool.hub[pb + q] = h;
+                p.pool.dist[pb + q] = (int32_t)d;
+            }
+        }
+        if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
+        if (p.stats && leader) {
+            int64_t* s = p.stats + (int64_t)h * STAT_COLS;
+            s[0] = twl<long long>(tw, T_SETTLED); s[1] = twl<long long>(tw, T_ARCS);
+            s[2] = twl<long long>(tw, T_NLAB); s[3] = early ? 1 : 0;
+            s[4] = it; s[5] = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
+        }
+        // the tree is done in every workgroup before the leader resets the words
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+    }
+}
+
 template <typename K, int WG>
 int launch_batched_t(const TreeParams& p, int phase, hipStream_t st) {
     const bool pr = p.poff != nullptr && p.pbound > 0;
@@ -691,6 +997,29 @@ int launch_plain_t(const TreeParams& p, int grid, int32_t root, int32_t* gstate,
     hipError_t e = hipLaunchCooperativeKernel((const void*)k_tree_plain<K, WG>, dim3(grid), dim3(WG),
                                               args, 0, st);
     return e == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int launch_team_t(const TreeParams& p, int W, int nteams, long long* tstate, int32_t* far2, hipStream_t st) {
+    TreeParams pp = p;
+    const bool pr = p.poff != nullptr && p.pbound > 0;
+    const size_t dl = pr ? (size_t)p.pbound * 4 : 0;
+    void* args[] = {(void*)&pp, (void*)&W, (void*)&tstate, (void*)&far2};
+    const void* f = pr ? (const void*)k_tree_team<K, WG, true> : (const void*)k_tree_team<K, WG, false>;
+    hipError_t e = hipLaunchCooperativeKernel(f, dim3(nteams * W), dim3(WG), args, dl, st);
+    return e == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int team_capacity_t() {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    // the pruned kernel with the largest prefix of a team launch bounds both
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tree_team<K, WG, true>, WG, MAX_PREFIX * 4) !=
+        hipSuccess)
+        return 0;
+    return per * cus;
 }
 
 template <typename K, int WG>
@@ -735,5 +1064,23 @@ int plain_grid_size(int key_bits, int wg) {
 }
 
 size_t plain_gstate_words() { return G_WORDS; }
+
+int launch_tree_team(const TreeParams& p, int key_bits, int wg, int team_size, int nteams,
+                     long long* tstate, int32_t* far2, hipStream_t st) {
+    if (team_size < 1 || nteams < 1) return -1;
+    if (key_bits == 32) {
+        if (wg == 512) return launch_team_t<uint32_t, 512>(p, team_size, nteams, tstate, far2, st);
+        if (wg == 1024) return launch_team_t<uint32_t, 1024>(p, team_size, nteams, tstate, far2, st);
+    } else {
+        if (wg == 512) return launch_team_t<uint64_t, 512>(p, team_size, nteams, tstate, far2, st);
+        if (wg == 1024) return launch_team_t<uint64_t, 1024>(p, team_size, nteams, tstate, far2, st);
+    }
+    return -1;
+}
+
+int team_capacity(int key_bits, int wg) {
+    if (key_bits == 32) return wg == 512 ? team_capacity_t<uint32_t, 512>() : team_capacity_t<uint32_t, 1024>();
+    return wg == 512 ? team_capacity_t<uint64_t, 512>() : team_capacity_t<uint64_t, 1024>();
+}
 
 }  // namespace chl

@@ -58,6 +58,7 @@ def test_random_small(seed):
     for kw in (dict(mode="batched", delta=1 + seed % 4, roots_in_flight=1 + seed % 7, wg_size=256, autotune=False),
                dict(mode="batched", delta=1000, wg_size=512, autotune=False, prune_hubs=-1),
                dict(mode="batched", delta=3, wg_size=1024, autotune=False, prune_hubs=4 * (1 + seed % 16)),
+               dict(mode="batched", delta=2 + seed % 5, autotune=False, team_wgs=2 + seed % 15),
                dict(mode="plain", delta=2, autotune=False)):
         L, off, hub, dist = gpu_labels(row, col, w, order, **kw)
         assert_same_labels(off, hub, dist, ref, str(kw))
@@ -77,19 +78,48 @@ def test_grid64_full():
     assert np.array_equal(q, qref)
 
 
-@pytest.mark.parametrize("k,wg,delta,eta", [(1, 256, 1, -1), (3, 512, 7, 16), (64, 1024, 50, 64),
-                                            (256, 256, 100, 4), (1024, 512, 400, 32), (2048, 256, 10_000, -1)])
-def test_parameter_invariance_rmat12(k, wg, delta, eta):
-    """Every (roots in flight, workgroup size, bucket width, pruning hubs)
-    gives the same labels."""
+@pytest.mark.parametrize("k,wg,delta,eta,team", [(1, 256, 1, -1, 0), (3, 512, 7, 16, 1), (64, 1024, 50, 64, 2),
+                                                 (256, 256, 100, 4, 16), (1024, 512, 400, 32, 5),
+                                                 (2048, 256, 10_000, -1, 0)])
+def test_parameter_invariance_rmat12(k, wg, delta, eta, team):
+    """Every (roots in flight, workgroup size, bucket width, pruning hubs,
+    workgroups per tree of the first levels) gives the same labels."""
     c = gg.make_config("rmat12s9")
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
-    _say("invariance", k, wg, delta, eta)
+    _say("invariance", k, wg, delta, eta, team)
     L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], mode="batched",
-                                   roots_in_flight=k, wg_size=wg, delta=delta, autotune=False, prune_hubs=eta if eta < 0 else 4 * (eta // 4 or 1))
+                                   roots_in_flight=k, wg_size=wg, delta=delta, autotune=False,
+                                   prune_hubs=eta if eta < 0 else 4 * (eta // 4 or 1), team_wgs=team)
     assert_same_labels(off, hub, dist, ref)
     st = L.stats(per_root=True)
     assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+
+
+@pytest.mark.parametrize("team", [1, 2, 3, 8, 16])
+def test_team_sizes_rmat14(team):
+    """The first levels grown by teams of 1..16 workgroups per tree: same
+    labels and the same labels per root as the oracle; with early
+    termination off as well."""
+    c = gg.make_config("rmat14s11")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    for early in (True, False):
+        _say("teams", team, early)
+        L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], team_wgs=team,
+                                       early_term=early, autotune=False, prune_hubs=1024)
+        assert_same_labels(off, hub, dist, ref)
+        st = L.stats(per_root=True)
+        assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+
+
+def test_team_grid():
+    """Teams on a grid (unpruned first level only when the probe drops the
+    pruning) give the oracle's labels."""
+    c = gg.make_config("grid128x128_5")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    for kw in (dict(team_wgs=4), dict(team_wgs=16, prune_hubs=256, autotune=False)):
+        _say("team grid", kw)
+        L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], **kw)
+        assert_same_labels(off, hub, dist, ref)
 
 
 def test_repeatable_rmat14():
