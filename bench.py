@@ -75,6 +75,154 @@ def serve_measure(chl, gg, c, row, col, w, order, stream, qout, q):
     return serving
 
 
+def serve_full(chl, gg, stream):
+    """The serving experiment at full size: the labelings of the R-MAT
+    scale-16 and the 1024x1024 diagonal-grid workloads resident, 10^7
+    uniform query pairs (half on each graph, in one Poisson stream) at 0.25,
+    0.5 and 0.9 of the server path's saturated rate, with 16 build requests
+    (R-MAT scales 10..16, seeds 500+i, weights [1,1000]) arriving over the
+    stream and admitted by HBM footprint. Every answer is checked against a
+    direct chl_query of the same labeling, every build against the same build
+    run alone."""
+    import numpy as np
+    import torch
+    from paper_1907_00140_amd import serve
+    dev = torch.device("cuda:0")
+    names = ("rmat16", "grid1024d")
+    res, qsets, direct = [], [], []
+    for k, nm in enumerate(names):
+        c = gg.make_config(nm)
+        d = [torch.from_numpy(c[f]).to(dev) for f in ("row_ptr", "col", "w", "order")]
+        t1 = time.perf_counter()
+        L = chl.build(*d, stream=stream)
+        torch.cuda.synchronize()
+        print("serve-full: built %s in %.2f s" % (nm, time.perf_counter() - t1), file=sys.stderr, flush=True)
+        pairs = gg.query_pairs(c["n"], 5_000_000, 702 + k)
+        direct.append(L.query(torch.from_numpy(pairs).to(dev), stream=stream).cpu().numpy())
+        res.append(L)
+        qsets.append(pairs)
+        del d
+    mk = lambda: serve.Server(mem_budget=64 << 30, max_batch=1 << 16, build_streams=2, build_wg=128)
+    # saturation: every query due at time 0
+    srv = mk()
+    gids = [srv.add_labels(L) for L in res]
+    tks = [srv.submit_queries(g, p, np.zeros(len(p))) for g, p in zip(gids, qsets)]
+    t1 = time.perf_counter()
+    srv.start()
+    srv.wait()
+    sat = sum(len(p) for p in qsets) / (time.perf_counter() - t1)
+    for tk, ref in zip(tks, direct):
+        assert np.array_equal(tk.out, ref)
+    srv.close()
+    print("serve-full: saturated %.3g queries/s" % sat, file=sys.stderr, flush=True)
+    bcfg = [gg.make_config("rmat%d_%d" % (10 + i % 7, i)) for i in range(16)]
+    alone = []
+    for c in bcfg:
+        Lb = chl.build(c["row_ptr"], c["col"], c["w"], c["order"], stream=stream)
+        alone.append([x.numpy() for x in Lb.export("cpu")])
+        Lb.free()
+    out = {"resident": list(names), "queries": int(sum(len(p) for p in qsets)), "saturated_qps": round(sat, 1),
+           "rates": []}
+    for f in (0.25, 0.5, 0.9):
+        rate = f * sat
+        span = sum(len(p) for p in qsets) / rate
+        tb = gg.poisson_arrivals(16, 16 / span, 900 + int(100 * f))
+        srv, tks, btk, wall = serve.open_loop(mk, res, qsets, rate, builds=list(zip(bcfg, tb)), seed=int(100 * f))
+        for tk, ref in zip(tks, direct):
+            assert np.array_equal(tk.out, ref), "served answers differ from chl_query"
+        for b, ref in zip(btk, alone):
+            assert b.status.value == 0, "build request failed: %d" % b.status.value
+            got = [x.numpy() for x in srv.labels(b.gid.value).export("cpu")]
+            assert all(np.array_equal(x, y) for x, y in zip(got, ref)), "served build differs from alone"
+        lat = np.concatenate([tk.lat for tk in tks])
+        tend = max(float(np.max(tk.t + tk.lat)) for tk in tks)
+        blat = np.array([b.lat.value for b in btk])
+        out["rates"].append({"fraction": f, "rate_qps": round(rate, 1),
+                             "achieved_qps": round(len(lat) / tend, 1),
+                             "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 2),
+                             "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 2),
+                             "per_graph_p99_us": [round(float(np.percentile(tk.lat, 99)) * 1e6, 2) for tk in tks],
+                             "build_latency_s": {"p50": round(float(np.median(blat)), 4),
+                                                 "max": round(float(blat.max()), 4)},
+                             "wall_s": round(wall, 3)})
+        srv.close()
+        print("serve-full:", json.dumps(out["rates"][-1]), file=sys.stderr, flush=True)
+    for L in res:
+        L.free()
+    return out
+
+
+def large_workloads(chl, gg, stream):
+    """The two million-vertex workloads: the 1024x1024 grid with 5% diagonal
+    shortcuts and R-MAT scale 20. Full labeling resident in HBM (build timed
+    after one untimed build that also tunes), label-size histogram (log2
+    bins of |L_v|), early-termination rate, exploration per label, 10^6
+    queries, and for the grid the plain one-root-per-launch form estimated
+    from 16 head roots and 64 rank-stratified roots."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    for nm in ("grid1024d", "rmat20"):
+        c = gg.make_config(nm)
+        d = [torch.from_numpy(c[f]).to(dev) for f in ("row_ptr", "col", "w", "order")]
+        pairs = torch.from_numpy(c["pairs"]).to(dev)
+        L = chl.build(*d, stream=stream)
+        torch.cuda.synchronize()
+        L.free()
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L = chl.build(*d, stream=stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            if len(times) < 2:
+                L.free()
+        st = L.stats()
+        off = L.offsets()
+        sizes = np.diff(off)
+        bins = np.bincount(np.floor(np.log2(np.maximum(sizes, 1))).astype(np.int64))
+        qo = L.query(pairs, stream=stream)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        qo = L.query(pairs, out=qo, stream=stream)
+        torch.cuda.synchronize()
+        qs = len(c["pairs"]) / (time.perf_counter() - t1)
+        L.free()
+        r = {"n": c["n"], "edges": c["m"], "build_s": round(min(times), 4), "build_s_runs": [round(t, 4) for t in times],
+             "labels": st["labels"], "als": round(st["labels"] / c["n"], 2), "max_label_size": int(sizes.max()),
+             "label_size_hist_log2": {"[%d,%d)" % (1 << k, 2 << k): int(v) for k, v in enumerate(bins) if v},
+             "early_termination_rate": round(st["early_trees"] / c["n"], 4),
+             "settled_per_tree": round(st["settled"] / c["n"], 1),
+             "explored_per_label": round(st["settled"] / max(1, st["labels"]), 2),
+             "gpu_arcs": st["arcs"], "gpu_arcs_per_s": round(st["arcs"] / min(times), 1),
+             "prune_hubs": st["prune_hubs"], "roots_in_flight": st["roots_in_flight"], "wg_size": st["wg_size"],
+             "delta": st["delta"], "key_bits": st["key_bits"],
+             "phases_ms": {"prep": round(st["prep_ms"], 1), "prefix": round(st["prefix_ms"], 1),
+                           "main": round(st["tree_ms"], 1), "assemble": round(st["assemble_ms"], 1)},
+             "queries_per_s": round(qs, 1)}
+        if nm == "grid1024d":
+            n = c["n"]
+            H, NS = 16, 64
+            stride = (n - H) // NS
+            tp = []
+            for roots in ((0, H, 1), (H, NS, stride)):
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                Lp = chl.build(*d, mode="plain", roots=roots, stream=stream)
+                torch.cuda.synchronize()
+                tp.append(time.perf_counter() - t1)
+                Lp.free()
+            r["plain_form"] = {"build_s_est": round(tp[0] + tp[1] * stride, 1),
+                               "method": "16 head roots + 64 rank-stratified roots (stride %d), "
+                                         "sum = head + sample * stride" % stride}
+        out[nm] = r
+        print("large:", nm, json.dumps(r), file=sys.stderr, flush=True)
+        del d, pairs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +231,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form estimate")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--large", action="store_true",
+                    help="also build the two million-vertex workloads and report them in a 'large' object")
+    ap.add_argument("--serve-full", action="store_true",
+                    help="also run the full-size serving experiment (two resident labelings, 10^7 queries "
+                         "at three rates, 16 builds); adds a 'serving_full' object")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -221,6 +374,9 @@ def main():
     if not args.no_serve:
         serving = serve_measure(chl, gg, c, row, col, w, order, stream, qout, q)
 
+    large = large_workloads(chl, gg, stream) if args.large else None
+    serving_full = serve_full(chl, gg, stream) if args.serve_full else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -258,6 +414,10 @@ def main():
                       "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if serving_full is not None:
+        out["serving_full"] = serving_full
+    if large is not None:
+        out["large"] = large
     print(json.dumps(out))
 
 

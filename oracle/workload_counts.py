@@ -4,7 +4,9 @@ every root, for the named workloads. These are the algorithmic work units of
 the build (used for GTEPS and the roofline's algorithmic bytes). Calls only
 the oracle and the input generators.
 
-Usage: python -m oracle.workload_counts [name ...]
+Usage: python -m oracle.workload_counts [--pruned-only] [name ...]
+(--pruned-only skips the unpruned trees, whose count takes hours on the
+million-vertex R-MAT graph.)
 """
 import json
 import os
@@ -29,7 +31,7 @@ def _sums(st, lo, hi):
 LEVELS = [16, 128, 1024, 4096]
 
 
-def counts(name, threads=None):
+def counts(name, threads=None, pruned_only=False):
     """Unpruned totals, and the work split (roots grown before the main
     phase / main phase) of each configuration the library's batched build
     can run: no pruning ("unpruned"), the 16 unpruned probe-level roots
@@ -37,19 +39,26 @@ def counts(name, threads=None):
     16, 128, 1024, 4096 with the main phase pruned by the 4096-hub
     prefix ("levels4096")."""
     c = gg.make_config(name)
-    t = time.time()
-    lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], mode=oracle.MODE_PLANT, threads=threads)
-    el = time.time() - t
-    st = lab.stats
-    n = len(st)
-    out = {"n": int(c["n"]), "m": int(c["m"]), "oracle_s": round(el, 2),
-           "threads": threads or min(16, os.cpu_count() or 1), **_sums(st, 0, n),
-           "split16": {"grown": 16, "pmain": 0, "head": _sums(st, 0, 16), "rest": _sums(st, 16, n)}}
+    n = int(c["n"])
+    out = {"n": n, "m": int(c["m"]), "threads": threads or min(16, os.cpu_count() or 1)}
+    lab = None
+    if not pruned_only:
+        t = time.time()
+        lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], mode=oracle.MODE_PLANT, threads=threads)
+        out["oracle_s"] = round(time.time() - t, 2)
+        st = lab.stats
+        out.update(_sums(st, 0, n))
+        out["split16"] = {"grown": 16, "pmain": 0, "head": _sums(st, 0, 16), "rest": _sums(st, 16, n)}
     gmax = min(LEVELS[-1], n // 2)
     lv = [g for g in LEVELS if g < gmax] + [gmax]
     if lv:
+        t = time.time()
         p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1], threads=threads)
-        assert p.total == lab.total
+        if lab is not None:
+            assert p.total == lab.total
+        else:
+            out["labels"] = int(p.total)
+            out["oracle_pruned_s"] = round(time.time() - t, 2)
         out["levels%d" % lv[-1]] = {"grown": lv[-1], "pmain": lv[-1], "head": _sums(p.stats, 0, lv[-1]),
                                     "rest": _sums(p.stats, lv[-1], n),
                                     "levels": [[a, b, _sums(p.stats, a, b)] for a, b in zip([0] + lv[:-1], lv)]}
@@ -57,9 +66,11 @@ def counts(name, threads=None):
 
 
 if __name__ == "__main__":
-    names = sys.argv[1:] or ["grid64", "rmat16"]
+    args = sys.argv[1:]
+    pruned_only = "--pruned-only" in args
+    names = [a for a in args if not a.startswith("--")] or ["grid64", "rmat16"]
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for nm in names:
-        data[nm] = counts(nm)
+        data[nm] = counts(nm, pruned_only=pruned_only)
         print(nm, data[nm], flush=True)
     json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)

@@ -208,6 +208,14 @@ class Labels:
                                           _stream_ptr(stream)), "chl_labels_export")
         return off, hub[:total], dist[:total]
 
+    def offsets(self, stream=None):
+        """offsets int64[n+1] (by input id) on the host, without the label arrays."""
+        n, _ = self.info()
+        off = np.zeros(n + 1, np.int64)
+        _check(self.lib.chl_labels_export(self._h, off.ctypes.data, None, None, 1, _stream_ptr(stream)),
+               "chl_labels_export")
+        return off
+
     def hub_vertex(self):
         n, _ = self.info()
         out = np.zeros(n, np.int32)

@@ -133,7 +133,7 @@ struct Build {
     int32_t* gstate = nullptr;         // plain form state words
     Pool pool{};
     int64_t* stats = nullptr;
-    // rank-prefix pruning: labels found so far, by rank position, sorted
+    // rank-prefix pruning: labels found so far, grouped by rank position
     const int64_t* poff = nullptr;
     const uint64_t* plab = nullptr;
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
@@ -338,30 +338,17 @@ int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int ear
     return 0;
 }
 
-uint64_t graph_signature(const chl_graph* g, const int32_t* order, hipStream_t st) {
+uint64_t graph_signature(const chl_graph* g, const int32_t* order, int64_t* dev_tmp, hipStream_t st) {
     // a few row offsets, arcs and ranking entries sampled at fixed positions
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
     mix((uint64_t)g->n);
     mix((uint64_t)g->n_arcs);
-    int64_t r[16] = {};
-    int32_t c[16] = {}, w[16] = {}, rk[16] = {};
-    for (int i = 0; i < 16; i++) {
-        const int64_t v = (int64_t)g->n * i / 16;
-        const int64_t e = g->n_arcs ? g->n_arcs * i / 16 : 0;
-        (void)hipMemcpyAsync(&r[i], g->row_ptr + v, 8, hipMemcpyDeviceToHost, st);
-        (void)hipMemcpyAsync(&rk[i], order + v, 4, hipMemcpyDeviceToHost, st);
-        if (g->n_arcs) {
-            (void)hipMemcpyAsync(&c[i], g->col + e, 4, hipMemcpyDeviceToHost, st);
-            (void)hipMemcpyAsync(&w[i], g->w + e, 4, hipMemcpyDeviceToHost, st);
-        }
-    }
-    (void)hipStreamSynchronize(st);
-    for (int i = 0; i < 16; i++) {
-        mix((uint64_t)r[i]);
-        mix((uint64_t)(uint32_t)c[i] << 32 | (uint32_t)w[i]);
-        mix((uint64_t)(uint32_t)rk[i]);
-    }
+    int64_t smp[64] = {};
+    if (launch_sample_input(g->n, g->n_arcs, g->row_ptr, g->col, g->w, order, dev_tmp, st) == 0 &&
+        hipMemcpyAsync(smp, dev_tmp, sizeof(smp), hipMemcpyDeviceToHost, st) == hipSuccess)
+        (void)hipStreamSynchronize(st);
+    for (int i = 0; i < 64; i++) mix((uint64_t)smp[i]);
     return h;
 }
 
@@ -547,7 +534,12 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     A.drop(cnt);
     S.prep_ms = tprep.stop();
     B.g = RGraph{n, B.m, rrow, rarc};
-    B.sig = graph_signature(g, order, st);
+    {
+        int64_t* smp = A.get<int64_t>(64);
+        if (!smp) return CHL_ERR_OOM;
+        B.sig = graph_signature(g, order, smp, st);
+        A.drop(smp);
+    }
     // 32-bit keys are exact when no simple path can reach 2^31 - 1
     B.key_bits = ((double)(n - 1) * (double)B.maxw <= 2147483646.0) ? 32 : 64;
     S.key_bits = B.key_bits;

@@ -80,11 +80,9 @@ int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* co
     if (used > 0)
         hipLaunchKernelGGL(k_count, dim3(g(used)), dim3(256), 0, st, pool.v, used, (const int32_t*)nullptr, count);
     if (launch_scan_i32_to_i64(count, offsets, n, scan_temp, st)) return -1;
-    if (used > 0) {
+    if (used > 0)
         hipLaunchKernelGGL(k_scatter, dim3(g(used)), dim3(256), 0, st, pool.v, pool.hub, pool.dist, used,
                            (const int32_t*)nullptr, offsets, fill, lab);
-        if (launch_segsort_u64(lab, offsets, n, (int64_t)used, nullptr, st)) return -1;
-    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -79,8 +79,8 @@ struct TreeParams {
     int32_t* nfailed;
     int32_t* far2;          // plain form: filtered far list, n entries
     int32_t root_base;      // batched form without a root list: root = root_base + counter
-    // rank-prefix pruning: the labels found so far, by vertex (rank position)
-    // and sorted by hub, plab[poff[v] .. poff[v+1]) = (hub << 32) | dist;
+    // rank-prefix pruning: the labels found so far, grouped by vertex (rank
+    // position), plab[poff[v] .. poff[v+1]) = (hub << 32) | dist;
     // trees of roots >= pbound prune with the hubs [0, pbound) (their labels
     // are complete); poff == NULL or pbound == 0 disables pruning
     const int64_t* poff;
@@ -103,6 +103,9 @@ int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order,
                         hipStream_t st);
 int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc,
                            int32_t* err, hipStream_t st);
+// out[64]: 16 samples x (row offset, ranking entry, neighbour, weight)
+int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const int32_t* w,
+                        const int32_t* order, int64_t* out, hipStream_t st);
 
 // scan.hip: exclusive prefix sum of int64 in[n] into out[n+1] (out[n] = total)
 size_t scan_temp_bytes(int64_t n);
@@ -137,7 +140,8 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
                     hipStream_t st);
 
 // assemble.hip: labels of the pool entries [0, used) grouped by vertex
-// (rank position) and sorted by hub, as (hub << 32) | dist words
+// (rank position), as (hub << 32) | dist words; the pruning test takes a
+// minimum over a vertex's entries, so their order within a vertex is free
 int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
                          int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st);
 constexpr int MAX_PREFIX = 4096;   // largest pruning prefix (root distances live in LDS)

@@ -145,6 +145,28 @@ int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order,
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// 16 row offsets, ranking entries, neighbours and weights at fixed positions
+// of the input (the signature that keys the tuning caches).
+__global__ void k_sample(int32_t n, int64_t m, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                         const int32_t* __restrict__ w, const int32_t* __restrict__ order, int64_t* __restrict__ out) {
+    const int i = threadIdx.x;
+    if (i < 16) {
+        const int64_t v = (int64_t)n * i / 16;
+        const int64_t e = m ? m * i / 16 : 0;
+        out[4 * i] = row[v];
+        out[4 * i + 1] = order[v];
+        out[4 * i + 2] = m ? col[e] : 0;
+        out[4 * i + 3] = m ? w[e] : 0;
+    }
+}
+
+int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const int32_t* w,
+                        const int32_t* order, int64_t* out, hipStream_t st) {
+    if (n <= 0) return -1;
+    hipLaunchKernelGGL(k_sample, dim3(1), dim3(64), 0, st, n, m, row_ptr, col, w, order, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc, int32_t* err,
                            hipStream_t st) {
     hipLaunchKernelGGL(k_sym, dim3(grid_for((int64_t)n * 64, 256)), dim3(256), 0, st, n, rrow, rarc, err);

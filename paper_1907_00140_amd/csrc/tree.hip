@@ -227,18 +227,17 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                 // shortest path through a hub that outranks the root; either
                 // way it cannot lead to a label, and a vertex whose true key
                 // is clean never has such a hub on its shortest paths, so
-                // dropping the candidate changes no label. u's list is sorted
-                // by hub: read it 8 entries at a time, most important first.
+                // dropping the candidate changes no label. u's entries are read
+                // 8 at a time until one prunes.
                 const int64_t lb = poff[u], le = poff[u + 1];
-                bool more = true;
-                for (int64_t i = lb; i < le && cand && more; i += 8) {
+                for (int64_t i = lb; i < le && cand; i += 8) {
                     uint64_t lx[8];
 #pragma unroll
                     for (int z = 0; z < 8; z++) lx[z] = i + z < le ? plab[i + z] : ~0ull;
 #pragma unroll
                     for (int z = 0; z < 8; z++) {
                         const uint32_t x = (uint32_t)(lx[z] >> 32);
-                        if (x >= pbound) { more = false; continue; }
+                        if (x >= pbound) continue;
                         const uint32_t a = dh[x];
                         if (a != 0xFFFFFFFFu && (uint64_t)a + (uint32_t)lx[z] <= nd) cand = false;
                     }

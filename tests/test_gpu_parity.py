@@ -76,6 +76,7 @@ def test_grid64_full():
     qref = oracle.query(ref, c["pairs"])
     q = L.query(c["pairs"]).cpu().numpy()
     assert np.array_equal(q, qref)
+    assert np.array_equal(L.offsets(), ref.offsets)
 
 
 @pytest.mark.parametrize("k,wg,delta,eta,team", [(1, 256, 1, -1, 0), (3, 512, 7, 16, 1), (64, 1024, 50, 64, 2),
