@@ -600,12 +600,13 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         };
         // level 0
         int32_t g = std::min<int32_t>(16, gmax);
-        // the first levels hold the largest trees: a full 1024-thread
-        // workgroup each. The unpruned trees of level 0 span the graph and
-        // run fastest with narrow buckets (little re-relaxation); pruned
-        // trees are small and latency bound, so wide buckets (fewer rounds)
-        // serve them better (measured on R-MAT scales 16 and 20)
-        const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 8));
+        // the first levels hold the largest trees: 1024-thread workgroups,
+        // teams of them for the narrow levels. Buckets of half the mean
+        // weight for the unpruned trees of level 0 (wider ones cost
+        // re-relaxation, narrower ones team barriers), twice the mean weight
+        // for the pruned levels, whose trees are smaller and latency bound
+        // (measured on R-MAT scales 16 and 20)
+        const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 2));
         const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
         // levels with fewer trees than the device holds 1024-thread
         // workgroups run as teams of workgroups, one tree per team
@@ -616,10 +617,16 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             tc.nteams = std::min<int>(std::min<int>(nr, tcap / std::max(1, tc.size)), s1.k);
             return tc.size >= 2;
         };
+        // team buffers for the largest team launch of any level schedule
         int tmax = 0;
-        for (int32_t a = 0, b = g; a < gmax; a = b, b = std::min<int32_t>(gmax, 8 * b)) {
+        for (int32_t f : {2, 8})
+            for (int32_t a = g, b = std::min<int32_t>(gmax, f * g); a < gmax; a = b, b = std::min<int32_t>(gmax, f * b)) {
+                TeamCfg tc;
+                if (team_shape(b - a, tc)) tmax = std::max(tmax, tc.nteams);
+            }
+        {
             TeamCfg tc;
-            if (team_shape(b - a, tc)) tmax = std::max(tmax, tc.nteams);
+            if (team_shape(g, tc)) tmax = std::max(tmax, tc.nteams);
         }
         int32_t* tfar2 = tmax ? A.get<int32_t>((size_t)tmax * n) : nullptr;
         long long* tstate = tmax ? A.get<long long>((size_t)tmax * TEAM_WORDS) : nullptr;
@@ -631,9 +638,11 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             return &tc;
         };
         TeamCfg tc0;
+        double level_ms = B.kernel_ms;
         if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
                                 team_for(g, tc0)))
             return r;
+        level_ms = B.kernel_ms - level_ms;
         if (int r = regroup()) return r;
         grown = g;
         bool probed = false;
@@ -678,12 +687,19 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         B.pbound = 0;
         if (keep) {
             while (g < gmax) {
-                const int32_t g2 = std::min<int32_t>(gmax, 8 * g);
+                // a level that kept the device busy for long was bound by its
+                // work: grow the prefix by 2 so that the next level is pruned
+                // by more hubs; short levels are bound by the latency of their
+                // trees: grow by 8, to have fewer of them (R-MAT scale 20 and
+                // scale 16 respectively)
+                const int32_t g2 = std::min<int32_t>(gmax, (level_ms > 5.0 ? 2 : 8) * g);
                 B.pbound = g;
                 TeamCfg tc;
+                level_ms = B.kernel_ms;
                 if (int r = run_batched(A, B, s1, 1024, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
                                         team_for(g2 - g, tc)))
                     return r;
+                level_ms = B.kernel_ms - level_ms;
                 if (int r = regroup()) return r;
                 g = g2;
             }
@@ -823,16 +839,15 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             return 0;
         }
     }
-    // probe: the first roots (largest trees) and a rank-stratified sample
+    // probe: a rank-stratified sample of the roots of the main phase (the
+    // roots before it are done), large enough that a trial measures the
+    // throughput of many trees in flight rather than the latency of a few
+    // large ones: 1/32 of the roots, at least 2048, at most 32768
     std::vector<int32_t> probe;
-    // the head trees span the whole graph: fewer of them on large graphs;
-    // the trees of the common-label roots are done already
     const int32_t r0 = B.grown;
-    int32_t head = std::min<int32_t>(n - r0, n > (1 << 18) ? 32 : 128);
-    for (int32_t r = 0; r < head; r++) probe.push_back(r0 + r);
-    int32_t strata = std::min<int32_t>(n - r0 - head, n > (1 << 18) ? 256 : 384);
-    for (int32_t i = 0; i < strata; i++)
-        probe.push_back(r0 + head + (int32_t)((int64_t)(n - r0 - head) * i / strata));
+    const int32_t rest = n - r0;
+    const int32_t strata = std::min<int32_t>(rest, std::max<int32_t>(2048, std::min<int32_t>(32768, rest / 32)));
+    for (int32_t i = 0; i < strata; i++) probe.push_back(r0 + (int32_t)((int64_t)rest * i / strata));
     if (probe.empty()) return 0;
     int64_t* saved_stats = B.stats;
     B.stats = nullptr;              // probe runs leave no statistics
@@ -843,10 +858,8 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     Slots s{};
     int kcur = 0;
     std::map<std::tuple<int, int, int64_t>, double> seen;
-    auto trial = [&](int kk, int w, int64_t d) -> int {
-        kk = std::max(1, std::min(kk, kmax));
-        d = std::max<int64_t>(1, d);
-        if (seen.count({kk, w, d})) return 0;
+    // one timed run of the probe roots (kk, w, d already clamped)
+    auto time_once = [&](int kk, int w, int64_t d, double& ms) -> int {
         if (kk != kcur) {
             free_slots(A, s);
             if (int r = alloc_slots(A, B, kk, s, st)) return r;
@@ -857,7 +870,15 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         if (int r = run_batched(A, B, s, w, d, o.early_term, probe.data(), (int32_t)probe.size(), st,
                                 &launches, 1))
             return r;
-        double ms = t.stop();
+        ms = t.stop();
+        return 0;
+    };
+    auto trial = [&](int kk, int w, int64_t d) -> int {
+        kk = std::max(1, std::min(kk, kmax));
+        d = std::max<int64_t>(1, d);
+        if (seen.count({kk, w, d})) return 0;
+        double ms = 0;
+        if (int r = time_once(kk, w, d, ms)) return r;
         seen[{kk, w, d}] = ms;
         if (ms < best) { best = ms; bv = TuneVal{kk, w, d, B.pbound}; }
         return 0;
@@ -880,6 +901,20 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         int kb = bv.k;
         for (int kk : {kb / 2, kb * 2})
             if (int r = trial(kk, bv.wg, bv.delta)) return r;
+    }
+    // time the two best settings once more and keep the faster in sum:
+    // single trials of a few milliseconds are noisy
+    if (seen.size() >= 2) {
+        std::vector<std::pair<double, std::tuple<int, int, int64_t>>> rank;
+        for (auto& kv : seen) rank.push_back({kv.second, kv.first});
+        std::sort(rank.begin(), rank.end());
+        double best2 = 1e30;
+        for (int i = 0; i < 2; i++) {
+            auto [kk, w, d] = rank[i].second;
+            double ms = 0;
+            if (int r = time_once(kk, w, d, ms)) return r;
+            if (rank[i].first + ms < best2) { best2 = rank[i].first + ms; bv = TuneVal{kk, w, d, B.pbound}; }
+        }
     }
     free_slots(A, s);
     B.stats = saved_stats;
