@@ -578,7 +578,12 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         if (A.oom) return CHL_ERR_OOM;
         uint64_t* plab = nullptr;
         size_t plab_cap = 0;
-        const int kpre = std::min(512, std::max(1, (int)(std::min<size_t>(4096, (size_t)(1ull << 33) / std::max<size_t>(1, slot_bytes(n, B.key_bits))))));
+        // trees in flight and workgroup size of the levels: 512 and 1024
+        // unless the caller fixed them (a caller that shares the device, such
+        // as the server, caps both)
+        const int kcap = o.roots_in_flight > 0 ? std::min(512, o.roots_in_flight) : 512;
+        const int lwg = o.wg_size ? o.wg_size : 1024;
+        const int kpre = std::min(kcap, std::max(1, (int)(std::min<size_t>(4096, (size_t)(1ull << 33) / std::max<size_t>(1, slot_bytes(n, B.key_bits))))));
         Slots s1{};
         if (int r = alloc_slots(A, B, kpre, s1, st)) return r;
         HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
@@ -608,9 +613,9 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         // (measured on R-MAT scales 16 and 20)
         const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 2));
         const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
-        // levels with fewer trees than the device holds 1024-thread
-        // workgroups run as teams of workgroups, one tree per team
-        const int tcap = o.team_wgs == 1 ? 0 : team_capacity(B.key_bits, 1024);
+        // levels with fewer trees than the device holds workgroups of that
+        // size run as teams of workgroups, one tree per team
+        const int tcap = o.team_wgs == 1 || lwg < 512 ? 0 : team_capacity(B.key_bits, lwg);
         auto team_shape = [&](int32_t nr, TeamCfg& tc) -> bool {
             if (tcap < 2 || nr <= 0 || 2 * nr > tcap) return false;
             tc.size = std::min(o.team_wgs ? o.team_wgs : 16, tcap / nr);
@@ -639,7 +644,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         };
         TeamCfg tc0;
         double level_ms = B.kernel_ms;
-        if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
+        if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
                                 team_for(g, tc0)))
             return r;
         level_ms = B.kernel_ms - level_ms;
@@ -670,7 +675,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             for (int on = 0; on < 2; on++) {
                 B.pbound = on ? g : 0;
                 HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
-                if (int r = run_batched(A, B, s1, 1024, dl, o.early_term, probe.data(), (int32_t)probe.size(), st,
+                if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, probe.data(), (int32_t)probe.size(), st,
                                         &launches, 1))
                     return r;
                 HIPCHK(hipMemcpy(rows.data(), B.stats, rows.size() * 8, hipMemcpyDeviceToHost));
@@ -696,7 +701,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
                 B.pbound = g;
                 TeamCfg tc;
                 level_ms = B.kernel_ms;
-                if (int r = run_batched(A, B, s1, 1024, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
+                if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
                                         team_for(g2 - g, tc)))
                     return r;
                 level_ms = B.kernel_ms - level_ms;
