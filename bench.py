@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "rmat16"
 COUNTS = os.path.join(ROOT, "tests", "golden", "workload_counts.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_tree_batched_rmat16.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_tree_rmat16.json")
 # the tree kernel and the host code that picks its launches: byte counters
 # taken for other sources no longer describe the kernel
 TREE_SRC = [os.path.join(ROOT, "paper_1907_00140_amd", "csrc", f) for f in ("tree.hip", "api.cpp")]

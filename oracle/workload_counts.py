@@ -4,9 +4,11 @@ every root, for the named workloads. These are the algorithmic work units of
 the build (used for GTEPS and the roofline's algorithmic bytes). Calls only
 the oracle and the input generators.
 
-Usage: python -m oracle.workload_counts [--pruned-only] [name ...]
+Usage: python -m oracle.workload_counts [--pruned-only | --no-levels] [name ...]
 (--pruned-only skips the unpruned trees, whose count takes hours on the
-million-vertex R-MAT graph.)
+million-vertex R-MAT graph; --no-levels skips the pruned trees, which the
+build does not use on grids and whose prefix queries over grid-sized label
+sets take hours.)
 """
 import json
 import os
@@ -29,15 +31,33 @@ def _sums(st, lo, hi):
 
 
 LEVELS = [16, 128, 1024, 4096]
+LEVEL0 = 16
+LEVEL_LABELS_X2 = 1 << 21
 
 
-def counts(name, threads=None, pruned_only=False):
+def level_bounds(labels_per_root, gmax):
+    """The pruning-level schedule of the batched build: roots [0, 16) first;
+    after a level whose roots have at least 2^21 labels in total the next
+    level is twice as large a prefix, else eight times, up to gmax. Labels
+    per root do not depend on the schedule, so any run's counts fix it."""
+    g = min(LEVEL0, gmax)
+    lv = [g]
+    lab = int(labels_per_root[0:g].sum())
+    while g < gmax:
+        g2 = min(gmax, (2 if lab >= LEVEL_LABELS_X2 else 8) * g)
+        lab = int(labels_per_root[g:g2].sum())
+        lv.append(g2)
+        g = g2
+    return lv
+
+
+def counts(name, threads=None, pruned_only=False, levels=True):
     """Unpruned totals, and the work split (roots grown before the main
     phase / main phase) of each configuration the library's batched build
     can run: no pruning ("unpruned"), the 16 unpruned probe-level roots
-    followed by unpruned trees ("split16"), and pruning in levels
-    16, 128, 1024, 4096 with the main phase pruned by the 4096-hub
-    prefix ("levels4096")."""
+    followed by unpruned trees ("split16"), and pruning in the levels of
+    level_bounds() up to 4096 (or n/2) with the main phase pruned by that
+    whole prefix ("levels4096")."""
     c = gg.make_config(name)
     n = int(c["n"])
     out = {"n": n, "m": int(c["m"]), "threads": threads or min(16, os.cpu_count() or 1)}
@@ -51,16 +71,21 @@ def counts(name, threads=None, pruned_only=False):
         out["split16"] = {"grown": 16, "pmain": 0, "head": _sums(st, 0, 16), "rest": _sums(st, 16, n)}
     gmax = min(LEVELS[-1], n // 2)
     lv = [g for g in LEVELS if g < gmax] + [gmax]
-    if lv:
+    if lv and levels:
         t = time.time()
         p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1], threads=threads)
+        lv2 = level_bounds(p.stats[:, 2], gmax)
+        if lv2 != lv:
+            lv = lv2
+            p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1],
+                                  threads=threads)
         if lab is not None:
             assert p.total == lab.total
         else:
             out["labels"] = int(p.total)
             out["oracle_pruned_s"] = round(time.time() - t, 2)
         out["levels%d" % lv[-1]] = {"grown": lv[-1], "pmain": lv[-1], "head": _sums(p.stats, 0, lv[-1]),
-                                    "rest": _sums(p.stats, lv[-1], n),
+                                    "rest": _sums(p.stats, lv[-1], n), "bounds": lv,
                                     "levels": [[a, b, _sums(p.stats, a, b)] for a, b in zip([0] + lv[:-1], lv)]}
     return out
 
@@ -68,9 +93,10 @@ def counts(name, threads=None, pruned_only=False):
 if __name__ == "__main__":
     args = sys.argv[1:]
     pruned_only = "--pruned-only" in args
+    levels = "--no-levels" not in args
     names = [a for a in args if not a.startswith("--")] or ["grid64", "rmat16"]
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for nm in names:
-        data[nm] = counts(nm, pruned_only=pruned_only)
+        data[nm] = counts(nm, pruned_only=pruned_only, levels=levels)
         print(nm, data[nm], flush=True)
     json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)

@@ -144,6 +144,10 @@ struct Build {
     uint64_t sig = 0;                    // graph and ranking signature (tuning caches)
 };
 
+// labels emitted by a pruning level above which the next level is only
+// twice as large (else eight times)
+constexpr unsigned long long LEVEL_LABELS_X2 = 1ull << 21;
+
 size_t slot_bytes(int32_t n, int key_bits) {
     return (size_t)n * (key_bits / 8 + 4 + 12) + (size_t)((n + 7) / 8) * 4;
 }
@@ -643,12 +647,11 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
             return &tc;
         };
         TeamCfg tc0;
-        double level_ms = B.kernel_ms;
         if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
                                 team_for(g, tc0)))
             return r;
-        level_ms = B.kernel_ms - level_ms;
         if (int r = regroup()) return r;
+        unsigned long long level_labels = B.cursor_base;
         grown = g;
         bool probed = false;
         bool keep = o.prune_hubs > 0 || !o.autotune;
@@ -692,20 +695,21 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         B.pbound = 0;
         if (keep) {
             while (g < gmax) {
-                // a level that kept the device busy for long was bound by its
-                // work: grow the prefix by 2 so that the next level is pruned
-                // by more hubs; short levels are bound by the latency of their
-                // trees: grow by 8, to have fewer of them (R-MAT scale 20 and
-                // scale 16 respectively)
-                const int32_t g2 = std::min<int32_t>(gmax, (level_ms > 5.0 ? 2 : 8) * g);
+                // a level whose trees emitted many labels did much work: grow
+                // the prefix by 2, so that the next level is pruned by more
+                // hubs; after a small level, whose time is the latency of its
+                // trees, grow by 8, to have fewer levels (the labels of a
+                // root do not depend on the schedule, so neither does the
+                // schedule itself)
+                const int32_t g2 = std::min<int32_t>(gmax, (level_labels >= LEVEL_LABELS_X2 ? 2 : 8) * g);
                 B.pbound = g;
                 TeamCfg tc;
-                level_ms = B.kernel_ms;
+                const unsigned long long before = B.cursor_base;
                 if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
                                         team_for(g2 - g, tc)))
                     return r;
-                level_ms = B.kernel_ms - level_ms;
                 if (int r = regroup()) return r;
+                level_labels = B.cursor_base - before;
                 g = g2;
             }
             grown = g;
