@@ -214,6 +214,9 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.roots = roots;
     p.stats = B.stats;
     p.root_base = root_base;
+    // many small trees per slot: take the roots several at a time so that
+    // the queue counter is not contended (rank order is kept within 16)
+    p.pop_batch = std::max(1, std::min(16, nroots / std::max(1, 8 * s.k)));
     p.poff = B.poff;
     p.plab = B.plab;
     p.pbound = B.pbound;
@@ -850,13 +853,18 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     // probe: a rank-stratified sample of the roots of the main phase (the
     // roots before it are done), large enough that a trial measures the
-    // throughput of many trees in flight rather than the latency of a few
-    // large ones: 1/32 of the roots, at least 2048, at most 32768
+    // throughput of many trees per slot rather than the latency of a few
+    // large ones or the launch: grown from 2048 roots by 4x until one run
+    // takes 10 ms (at most 262144 roots, or all of them)
     std::vector<int32_t> probe;
     const int32_t r0 = B.grown;
     const int32_t rest = n - r0;
-    const int32_t strata = std::min<int32_t>(rest, std::max<int32_t>(2048, std::min<int32_t>(32768, rest / 32)));
-    for (int32_t i = 0; i < strata; i++) probe.push_back(r0 + (int32_t)((int64_t)rest * i / strata));
+    auto make_probe = [&](int32_t strata) {
+        probe.clear();
+        for (int32_t i = 0; i < strata; i++) probe.push_back(r0 + (int32_t)((int64_t)rest * i / strata));
+    };
+    int32_t strata = std::min<int32_t>(rest, 2048);
+    make_probe(strata);
     if (probe.empty()) return 0;
     int64_t* saved_stats = B.stats;
     B.stats = nullptr;              // probe runs leave no statistics
@@ -896,6 +904,16 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     // size at a fixed thread count, then trees in flight
     const int k0 = o.roots_in_flight ? k : std::min(kmax, 512);
     const int w0 = o.wg_size ? wg : 512;
+    {
+        const int64_t d0 = o.delta ? delta : std::max<int64_t>(1, (int64_t)wmean);
+        for (;;) {
+            double ms = 0;
+            if (int r = time_once(std::max(1, std::min(k0, kmax)), w0, d0, ms)) return r;
+            if (ms >= 10.0 || strata >= std::min<int32_t>(rest, 1 << 18)) break;
+            strata = std::min<int32_t>(std::min<int32_t>(rest, 1 << 18), 4 * strata);
+            make_probe(strata);
+        }
+    }
     if (!o.delta) {
         for (double f : {1.0 / 64, 1.0 / 16, 0.25, 1.0, 4.0})
             if (int r = trial(k0, w0, (int64_t)(f * wmean))) return r;
@@ -903,13 +921,19 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         for (double f : {0.5, 2.0})
             if (int r = trial(k0, w0, (int64_t)(f * d0))) return r;
     }
-    if (!o.wg_size)
-        for (int w : {256, 1024})
-            if (int r = trial(o.roots_in_flight ? k : k0 * w0 / w, w, bv.delta)) return r;
-    if (!o.roots_in_flight) {
-        int kb = bv.k;
-        for (int kk : {kb / 2, kb * 2})
-            if (int r = trial(kk, bv.wg, bv.delta)) return r;
+    // then workgroup size x threads in flight (trees in flight = threads /
+    // workgroup size) at that bucket width
+    {
+        const int wgs[3] = {256, 512, 1024};
+        for (int w : wgs) {
+            if (o.wg_size && w != wg) continue;
+            if (o.roots_in_flight) {
+                if (int r = trial(k, w, bv.delta)) return r;
+                continue;
+            }
+            for (int threads : {1 << 17, 1 << 18, 1 << 19, 1 << 20})
+                if (int r = trial(threads / w, w, bv.delta)) return r;
+        }
     }
     // time the two best settings once more and keep the faster in sum:
     // single trials of a few milliseconds are noisy

@@ -79,6 +79,7 @@ struct TreeParams {
     int32_t* nfailed;
     int32_t* far2;          // plain form: filtered far list, n entries
     int32_t root_base;      // batched form without a root list: root = root_base + counter
+    int32_t pop_batch;      // batched form: queue positions taken per atomic (>= 1)
     // rank-prefix pruning: the labels found so far, grouped by vertex (rank
     // position), plab[poff[v] .. poff[v+1]) = (hub << 32) | dist;
     // trees of roots >= pbound prune with the hubs [0, pbound) (their labels

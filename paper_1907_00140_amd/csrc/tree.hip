@@ -279,6 +279,7 @@ struct BatchedLds {
     int32_t red32[WG / 64];
     int32_t ncur, cnt_next, cnt_far, cnt_touched, nkeep, far_clean;
     int32_t root;
+    int32_t bnext, bend;      // root queue positions taken by this workgroup, not yet grown
     unsigned long long umax;
     long long pool_base;
 };
@@ -296,7 +297,10 @@ struct BatchedLds {
 template <typename K, int WG, int SC>
 __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, const int32_t* cur,
                                          int32_t ncur, int64_t T) {
-    const int tid = threadIdx.x;
+    constexpr int NW = WG / 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // one reduction of (smallest pending distance, any pending vertex clean):
+    // the distance in the high bits, the clean flag in bit 0 of the OR half
     unsigned long long mn = ~0ull;
     int32_t cl = 0;
     for (int32_t i = tid; i < ncur; i += WG) {
@@ -305,9 +309,20 @@ __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, con
         mn = d < mn ? d : mn;
         cl |= (int32_t)(kv & 1);
     }
-    mn = block_reduce<WG>(mn, S.red64, ~0ull,
-        [](unsigned long long a, unsigned long long b) { return a < b ? a : b; });
-    cl = block_reduce<WG>(cl, S.red32, 0, [](int32_t a, int32_t b) { return a | b; });
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(mn, d);
+        mn = o < mn ? o : mn;
+        cl |= __shfl_xor(cl, d);
+    }
+    if (lane == 0) { S.red64[w] = mn; S.red32[w] = cl; }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NW; i++) {
+        mn = S.red64[i] < mn ? S.red64[i] : mn;
+        cl |= S.red32[i];
+    }
+    __syncthreads();
     unsigned long long lb = mn < (unsigned long long)T ? mn : (unsigned long long)T;
     return cl == 0 && lb > S.umax;
 }
@@ -329,13 +344,31 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     int32_t* lists = p.s.lists + slot * 3 * p.s.stride;
     int32_t* far = lists + 2 * p.s.stride;
     const int64_t delta = p.delta;
+    // dh is all ones between trees: a tree sets its root's entries and
+    // clears them when it is done
+    if (PRUNE)
+        for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
+    if (tid == 0) { S.bnext = 0; S.bend = 0; }
 
     for (;;) {
         if (tid == 0) {
+            // roots are taken from the queue pop_batch at a time (one atomic
+            // on the shared counter per batch); once the pool is full, the
+            // roots taken but not grown are handed back as failed
             int32_t r = -1;
-            if (__hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-                int32_t c = atomicAdd(p.next_root, 1);
-                if (c < p.nroots) r = p.roots ? p.roots[c] : p.root_base + c;
+            const bool stopped = __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (stopped) {
+                for (int32_t c = S.bnext; c < S.bend; c++)
+                    p.failed[atomicAdd(p.nfailed, 1)] = p.roots ? p.roots[c] : p.root_base + c;
+                S.bnext = S.bend;
+            } else if (S.bnext >= S.bend) {
+                const int32_t c = atomicAdd(p.next_root, p.pop_batch);
+                S.bnext = c;
+                S.bend = c < p.nroots ? min(p.nroots, c + p.pop_batch) : c;
+            }
+            if (S.bnext < S.bend) {
+                r = p.roots ? p.roots[S.bnext] : p.root_base + S.bnext;
+                S.bnext++;
             }
             S.root = r;
         }
@@ -343,15 +376,12 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         const int32_t h = S.root;
         if (h < 0) break;
         const bool prune = PRUNE && h >= p.pbound;
-        if (prune) {
-            for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
-            __syncthreads();
+        if (prune)
             for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
                 const uint32_t x = (uint32_t)(lx >> 32);
                 if (x < (uint32_t)p.pbound) dh[x] = (uint32_t)lx;
             }
-        }
 
         // ---- init: root key (0, clean) in near list 0
         if (tid == 0) {
@@ -376,7 +406,8 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                 const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
                 int32_t* cur = lists + (int64_t)(it & 1) * p.s.stride;
                 int32_t* next = lists + (int64_t)((it + 1) & 1) * p.s.stride;
-                if (p.early_term && S.far_clean == 0 && may_stop<K, WG, SC>(S, key, cur, ncur, T)) {
+                // (the first round holds only the root, which is clean)
+                if (p.early_term && it > 0 && S.far_clean == 0 && may_stop<K, WG, SC>(S, key, cur, ncur, T)) {
                     // drop the pending entries: clear their list bits
                     for (int32_t i = tid; i < ncur; i += WG) aand<SC>(&flags[cur[i] >> 3], ~(curbit << fshift(cur[i])));
                     for (int32_t i = tid; i < S.cnt_far; i += WG) aand<SC>(&flags[far[i] >> 3], ~(FAR_BIT << fshift(far[i])));
@@ -506,6 +537,12 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             s[0] = (int64_t)settled; s[1] = (int64_t)arcs; s[2] = nl; s[3] = early ? 1 : 0;
             s[4] = it; s[5] = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
         }
+        // every read of dh is behind the emission's barriers
+        if (prune)
+            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
+                const uint32_t x = (uint32_t)(p.plab[i] >> 32);
+                if (x < (uint32_t)p.pbound) dh[x] = 0xFFFFFFFFu;
+            }
         __syncthreads();
     }
 }
@@ -861,8 +898,11 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
                         break;
                     }
                 }
-                for (int32_t base = trank * WG; base < ncur; base += W * WG)
-                    relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
+                // the near list split evenly over the team's workgroups (a
+                // small frontier would otherwise leave most of them idle)
+                const int32_t chunk = min(WG, (ncur + W - 1) / W);
+                for (int32_t base = trank * chunk; base < ncur; base += W * chunk)
+                    relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(chunk, ncur - base), curbit,
                                            nextbit, h, T, touched, next, far, (ull*)&tw[T_TOUCHED],
                                            (ull*)&tw[T_CNT0 + (it + 1) % 3], (ull*)&tw[T_FAR],
                                            (ull*)&tw[T_FARCLEAN], (ull*)&tw[T_UMAX], p.poff, p.plab,
