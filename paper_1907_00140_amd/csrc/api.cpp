@@ -532,7 +532,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (launch_scan_i64(rdeg, rrow, n, scan_tmp, st)) return CHL_ERR_HIP;
     if (launch_renumber(n, B.m, g->row_ptr, g->col, g->w, order, pos, rrow, rarc, st)) return CHL_ERR_HIP;
     if (launch_segsort_u64(rarc, rrow, n, B.m, nullptr, st)) return CHL_ERR_HIP;
-    if (launch_check_symmetric(n, rrow, rarc, err, st)) return CHL_ERR_HIP;
+    if (launch_check_symmetric(n, B.m, rrow, rarc, err, st)) return CHL_ERR_HIP;
     HIPCHK(hipMemcpyAsync(hub_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(hv, err, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

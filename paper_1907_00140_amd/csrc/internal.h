@@ -102,7 +102,7 @@ int launch_renumber(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t*
                     int64_t* rrow, uint64_t* rarc, hipStream_t st);
 int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order, int64_t* rdeg,
                         hipStream_t st);
-int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc,
+int launch_check_symmetric(int32_t n, int64_t m, const int64_t* rrow, const uint64_t* rarc,
                            int32_t* err, hipStream_t st);
 // out[64]: 16 samples x (row offset, ranking entry, neighbour, weight)
 int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const int32_t* w,

@@ -36,8 +36,10 @@ __global__ void k_rows(int32_t n, int64_t m, const int64_t* __restrict__ row,
     }
 }
 
+// 256 threads per block; one atomic per block on the shared maximum
 __global__ void k_arcs(int32_t n, int64_t m, const int32_t* __restrict__ col,
                        const int32_t* __restrict__ w, int32_t* err, int32_t* maxw) {
+    __shared__ int32_t red[4];
     int32_t mx = 0;
     bool bad = false;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
@@ -47,7 +49,9 @@ __global__ void k_arcs(int32_t n, int64_t m, const int32_t* __restrict__ col,
         mx = max(mx, x);
     }
     for (int d = 32; d >= 1; d >>= 1) mx = max(mx, __shfl_xor(mx, d));
-    if ((threadIdx.x & 63) == 0) atomicMax(maxw, mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(maxw, max(max(red[0], red[1]), max(red[2], red[3])));
     if (bad) atomicOr(err, ERR_BIT_INVALID);
 }
 
@@ -86,26 +90,31 @@ __device__ __forceinline__ int64_t lower(const uint64_t* a, int64_t lo, int64_t 
 
 // every arc (p, u, w) must be matched by as many (u, p, w) as there are
 // (p, u, w): rows are sorted, so both counts are run lengths found by binary
-// search. One wave per row.
-__global__ void k_sym(int32_t n, const int64_t* __restrict__ rrow, const uint64_t* __restrict__ rarc,
+// search. One thread per arc (the first of its run does the check), so that
+// long rows spread over many threads; its row is found by binary search in
+// the row offsets.
+__global__ void k_sym(int32_t n, int64_t m, const int64_t* __restrict__ rrow, const uint64_t* __restrict__ rarc,
                       int32_t* err) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     bool bad = false;
-    for (int64_t p = wave; p < n; p += nwaves) {
-        int64_t b = rrow[p], e = rrow[p + 1];
-        for (int64_t i = b + lane; i < e; i += 64) {
-            uint64_t k = rarc[i];
-            if (i > b && rarc[i - 1] == k) continue;          // first of its run only
-            int64_t c1 = lower(rarc, i, e, k + 1) - i;
-            uint32_t u = (uint32_t)(k >> 32);
-            uint64_t kr = ((uint64_t)(uint32_t)p << 32) | (uint32_t)k;
-            int64_t ub = rrow[u], ue = rrow[u + 1];
-            int64_t l = lower(rarc, ub, ue, kr);
-            int64_t c2 = lower(rarc, l, ue, kr + 1) - l;
-            bad |= c1 != c2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        // row p of arc i: the last p with rrow[p] <= i
+        int64_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (rrow[mid] <= i) lo = mid; else hi = mid - 1;
         }
+        const int64_t p = lo, b = rrow[p], e = rrow[p + 1];
+        const uint64_t k = rarc[i];
+        if (i > b && rarc[i - 1] == k) continue;          // first of its run only
+        int64_t c1 = 1;
+        while (i + c1 < e && rarc[i + c1] == k) c1++;
+        const uint32_t u = (uint32_t)(k >> 32);
+        const uint64_t kr = ((uint64_t)(uint32_t)p << 32) | (uint32_t)k;
+        int64_t l = lower(rarc, rrow[u], rrow[u + 1], kr);
+        int64_t c2 = 0;
+        while (l + c2 < rrow[u + 1] && rarc[l + c2] == kr) c2++;
+        bad |= c1 != c2;
     }
     if (bad) atomicOr(err, ERR_BIT_INVALID);
 }
@@ -125,7 +134,8 @@ int launch_validate(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t*
     hipLaunchKernelGGL(k_order, dim3(grid_for(n, 256)), dim3(256), 0, st, n, order, pos, cnt, err);
     hipLaunchKernelGGL(k_rows, dim3(grid_for((int64_t)n + 1, 256)), dim3(256), 0, st, n, m, row_ptr, cnt, err);
     if (m > 0)
-        hipLaunchKernelGGL(k_arcs, dim3(grid_for(m, 256)), dim3(256), 0, st, n, m, col, w, err, maxw);
+        hipLaunchKernelGGL(k_arcs, dim3(grid_for(m, 256) < 2048 ? grid_for(m, 256) : 2048), dim3(256), 0, st, n, m,
+                           col, w, err, maxw);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -167,9 +177,9 @@ int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int3
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_check_symmetric(int32_t n, const int64_t* rrow, const uint64_t* rarc, int32_t* err,
+int launch_check_symmetric(int32_t n, int64_t m, const int64_t* rrow, const uint64_t* rarc, int32_t* err,
                            hipStream_t st) {
-    hipLaunchKernelGGL(k_sym, dim3(grid_for((int64_t)n * 64, 256)), dim3(256), 0, st, n, rrow, rarc, err);
+    if (m > 0) hipLaunchKernelGGL(k_sym, dim3(grid_for(m, 256)), dim3(256), 0, st, n, m, rrow, rarc, err);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
