@@ -85,9 +85,13 @@ struct Timer {
         (void)hipEventRecord(a, s);
     }
     double stop() {
-        float ms = 0;
-        (void)hipEventRecord(b, s);
+        record_end();
         (void)hipEventSynchronize(b);
+        return elapsed();
+    }
+    void record_end() { (void)hipEventRecord(b, s); }
+    double elapsed() {   // after the end event has completed
+        float ms = 0;
         (void)hipEventElapsedTime(&ms, a, b);
         return ms;
     }
@@ -96,6 +100,22 @@ struct Timer {
         (void)hipEventDestroy(b);
     }
 };
+
+// Small device-to-host readbacks (control words, error flags, samples) go
+// through pinned host memory, so that several of them queue on the stream
+// and complete with one synchronisation. One block per host thread, kept
+// until the process ends.
+struct HostCtl {
+    int32_t c32[16];
+    unsigned long long c64[4];
+    int64_t smp[64];
+    int64_t sums[4];
+};
+HostCtl* host_ctl() {
+    static thread_local HostCtl* h = nullptr;
+    if (!h && hipHostMalloc((void**)&h, sizeof(HostCtl), hipHostMallocDefault) != hipSuccess) h = nullptr;
+    return h;
+}
 
 // ---------------------------------------------------------------- tuning
 struct TuneKey {
@@ -142,6 +162,7 @@ struct Build {
     double kernel_ms = 0;                // event-timed production tree launches
     int64_t kernel_launches = 0;
     uint64_t sig = 0;                    // graph and ranking signature (tuning caches)
+    unsigned long long last_used = 0;    // pool cursor after the last tree launch
 };
 
 // labels emitted by a pruning level above which the next level is only
@@ -248,24 +269,32 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
         HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
         TreeParams p = params(B, s, delta, early, dev_roots, nroots, root_base);
+        HostCtl* hc = host_ctl();
+        if (!hc) return CHL_ERR_HIP;
+        if (team) HIPCHK(hipMemsetAsync(team->tstate, 0, (size_t)team->nteams * TEAM_WORDS * 8, st));
         {
+            // the launch is timed by events; the control words are read back
+            // behind it, and one synchronisation completes both
             Timer tk(st);
             if (team) {
-                HIPCHK(hipMemsetAsync(team->tstate, 0, (size_t)team->nteams * TEAM_WORDS * 8, st));
                 if (launch_tree_team(p, B.key_bits, wg, team->size, team->nteams, team->tstate, team->far2, st))
                     return CHL_ERR_HIP;
             } else if (launch_tree_batched(p, B.key_bits, wg, phase, st)) {
                 return CHL_ERR_HIP;
             }
-            const double ms = tk.stop();
+            tk.record_end();
+            HIPCHK(hipMemcpyAsync(hc->c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hc->c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            const double ms = tk.elapsed();
             if (phase != 1) { B.kernel_ms += ms; B.kernel_launches++; }
         }
         (*launches)++;
         int32_t c32[4];
         unsigned long long c64[2];
-        HIPCHK(hipMemcpyAsync(c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipMemcpyAsync(c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(c32, hc->c32, sizeof(c32));
+        std::memcpy(c64, hc->c64, sizeof(c64));
+        B.last_used = c64[0];
         if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
         if (c32[3] & ERR_BIT_TEAM) return CHL_ERR_HIP;
         if (!(c32[3] & ERR_BIT_POOL)) break;
@@ -351,11 +380,13 @@ uint64_t graph_signature(const chl_graph* g, const int32_t* order, int64_t* dev_
     auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
     mix((uint64_t)g->n);
     mix((uint64_t)g->n_arcs);
-    int64_t smp[64] = {};
+    HostCtl* hc = host_ctl();
+    if (!hc) return h;
+    std::memset(hc->smp, 0, sizeof(hc->smp));
     if (launch_sample_input(g->n, g->n_arcs, g->row_ptr, g->col, g->w, order, dev_tmp, st) == 0 &&
-        hipMemcpyAsync(smp, dev_tmp, sizeof(smp), hipMemcpyDeviceToHost, st) == hipSuccess)
+        hipMemcpyAsync(hc->smp, dev_tmp, sizeof(hc->smp), hipMemcpyDeviceToHost, st) == hipSuccess)
         (void)hipStreamSynchronize(st);
-    for (int i = 0; i < 64; i++) mix((uint64_t)smp[i]);
+    for (int i = 0; i < 64; i++) mix((uint64_t)hc->smp[i]);
     return h;
 }
 
@@ -523,20 +554,21 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     int32_t* err = B.ctl32 + 3;
     int32_t* maxw = B.ctl32 + 4;
     if (launch_validate(n, B.m, g->row_ptr, g->col, g->w, order, pos, cnt, err, maxw, st)) return CHL_ERR_HIP;
-    int32_t hv[2];
-    HIPCHK(hipMemcpyAsync(hv, err, 8, hipMemcpyDeviceToHost, st));
+    HostCtl* hc0 = host_ctl();
+    if (!hc0) return CHL_ERR_HIP;
+    HIPCHK(hipMemcpyAsync(hc0->c32, err, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (hv[0]) return CHL_ERR_INVALID_ARG;
-    B.maxw = std::max(1, hv[1]);
+    if (hc0->c32[0]) return CHL_ERR_INVALID_ARG;
+    B.maxw = std::max(1, hc0->c32[1]);
     if (launch_rank_degrees(n, g->row_ptr, order, rdeg, st)) return CHL_ERR_HIP;
     if (launch_scan_i64(rdeg, rrow, n, scan_tmp, st)) return CHL_ERR_HIP;
     if (launch_renumber(n, B.m, g->row_ptr, g->col, g->w, order, pos, rrow, rarc, st)) return CHL_ERR_HIP;
     if (launch_segsort_u64(rarc, rrow, n, B.m, nullptr, st)) return CHL_ERR_HIP;
     if (launch_check_symmetric(n, B.m, rrow, rarc, err, st)) return CHL_ERR_HIP;
     HIPCHK(hipMemcpyAsync(hub_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(hv, err, 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hc0->c32, err, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (hv[0]) return CHL_ERR_INVALID_ARG;
+    if (hc0->c32[0]) return CHL_ERR_INVALID_ARG;
     A.drop(rdeg);
     A.drop(cnt);
     S.prep_ms = tprep.stop();
@@ -595,9 +627,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         if (int r = alloc_slots(A, B, kpre, s1, st)) return r;
         HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
         auto regroup = [&]() -> int {
-            unsigned long long used = 0;
-            HIPCHK(hipMemcpyAsync(&used, B.ctl64, 8, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            const unsigned long long used = B.last_used;
             if (used > plab_cap) {
                 if (plab) A.drop(plab);
                 plab_cap = std::max<size_t>(used, 2 * plab_cap);
@@ -771,13 +801,15 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     S.kernel_launches = B.kernel_launches;
     S.launches = launches - prefix_launches;
     free_slots(A, s);
-    int32_t c32[4];
-    unsigned long long used = 0;
-    HIPCHK(hipMemcpyAsync(c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(&used, B.ctl64, 8, hipMemcpyDeviceToHost, st));
+    HostCtl* hc = host_ctl();
+    if (!hc) return CHL_ERR_HIP;
+    HIPCHK(hipMemcpyAsync(hc->c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hc->c64, B.ctl64, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    if (c32[3] & ERR_BIT_OVERFLOW) return CHL_ERR_DIST_OVERFLOW;
-    if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
+    const int32_t errw = hc->c32[3];
+    const unsigned long long used = hc->c64[0];
+    if (errw & ERR_BIT_OVERFLOW) return CHL_ERR_DIST_OVERFLOW;
+    if (errw & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
 
     // ---- assembly
     Timer tasm(st);
@@ -804,13 +836,17 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     // totals of the per-root statistics
     S.labels = (int64_t)used;
     if (B.stats) {
-        std::vector<int64_t> pr((size_t)n * STAT_COLS);
-        if (hipMemcpy(pr.data(), B.stats, (size_t)n * STAT_COLS * 8, hipMemcpyDeviceToHost) != hipSuccess) { delete L; return CHL_ERR_HIP; }
-        for (int32_t i = 0; i < n; i++) {
-            S.settled += pr[STAT_COLS * i];
-            S.arcs += pr[STAT_COLS * i + 1];
-            S.early_trees += pr[STAT_COLS * i + 3];
+        int64_t* dsum = A.get<int64_t>(4);
+        if (!dsum || hipMemsetAsync(dsum, 0, 32, st) != hipSuccess ||
+            launch_stat_sums(n, B.stats, dsum, st) ||
+            hipMemcpyAsync(hc->sums, dsum, 32, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            delete L;
+            return CHL_ERR_HIP;
         }
+        S.settled = hc->sums[0];
+        S.arcs = hc->sums[1];
+        S.early_trees = hc->sums[2];
         L->per_root = B.stats;
         A.release(B.stats);
     }

@@ -73,6 +73,38 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Totals of the per-root statistics columns 0 (settled), 1 (arcs) and 3
+// (stopped early) into sums[0..2]; 256 threads per block, one atomic per
+// block and column.
+__global__ void k_stat_sums(int32_t n, const int64_t* __restrict__ st, unsigned long long* __restrict__ sums) {
+    __shared__ unsigned long long red[3][4];
+    unsigned long long a = 0, b = 0, c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        a += (unsigned long long)st[i * STAT_COLS];
+        b += (unsigned long long)st[i * STAT_COLS + 1];
+        c += (unsigned long long)st[i * STAT_COLS + 3];
+    }
+    for (int d = 32; d >= 1; d >>= 1) {
+        a += __shfl_xor(a, d);
+        b += __shfl_xor(b, d);
+        c += __shfl_xor(c, d);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[0][w] = a; red[1][w] = b; red[2][w] = c; }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const unsigned long long t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (t) atomicAdd(&sums[threadIdx.x], t);
+    }
+}
+
+int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st) {
+    int grid = (int)std::min<int64_t>(1024, ((int64_t)n + 255) / 256);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(k_stat_sums, dim3(grid), dim3(256), 0, st, n, stats, (unsigned long long*)sums);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
                          int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st) {
     hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, count, (int64_t)n);

@@ -145,6 +145,9 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
 // minimum over a vertex's entries, so their order within a vertex is free
 int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
                          int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st);
+// assemble.hip: totals of the per-root statistics (settled, arcs, stopped
+// early) into sums[0..2] (zeroed by the caller)
+int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);
 constexpr int MAX_PREFIX = 4096;   // largest pruning prefix (root distances live in LDS)
 
 // query.hip
