@@ -153,17 +153,18 @@ def serve_full(chl, gg, stream):
 
 
 def large_workloads(chl, gg, stream):
-    """The two million-vertex workloads: the 1024x1024 grid with 5% diagonal
-    shortcuts and R-MAT scale 20. Full labeling resident in HBM (build timed
-    after one untimed build that also tunes), label-size histogram (log2
-    bins of |L_v|), early-termination rate, exploration per label, 10^6
-    queries, and for the grid the plain one-root-per-launch form estimated
-    from 16 head roots and 64 rank-stratified roots."""
+    """The other workloads: the 64x64 grid (10^4 queries), the 1024x1024 grid
+    with 5% diagonal shortcuts and R-MAT scale 20 (10^6 queries each). Full
+    labeling resident in HBM (build timed after one untimed build that also
+    tunes), label-size histogram (log2 bins of |L_v|), early-termination
+    rate, exploration per label, queries/s, and for the grids the plain
+    one-root-per-launch form estimated from head roots and rank-stratified
+    roots (64 + 256 on the small grid, 16 + 64 on the large one)."""
     import numpy as np
     import torch
     dev = torch.device("cuda:0")
     out = {}
-    for nm in ("grid1024d", "rmat20"):
+    for nm in ("grid64", "grid1024d", "rmat20"):
         c = gg.make_config(nm)
         d = [torch.from_numpy(c[f]).to(dev) for f in ("row_ptr", "col", "w", "order")]
         pairs = torch.from_numpy(c["pairs"]).to(dev)
@@ -202,9 +203,9 @@ def large_workloads(chl, gg, stream):
              "phases_ms": {"prep": round(st["prep_ms"], 1), "prefix": round(st["prefix_ms"], 1),
                            "main": round(st["tree_ms"], 1), "assemble": round(st["assemble_ms"], 1)},
              "queries_per_s": round(qs, 1)}
-        if nm == "grid1024d":
+        if nm.startswith("grid"):
             n = c["n"]
-            H, NS = 16, 64
+            H, NS = (64, 256) if n < 100_000 else (16, 64)
             stride = (n - H) // NS
             tp = []
             for roots in ((0, H, 1), (H, NS, stride)):
@@ -214,9 +215,9 @@ def large_workloads(chl, gg, stream):
                 torch.cuda.synchronize()
                 tp.append(time.perf_counter() - t1)
                 Lp.free()
-            r["plain_form"] = {"build_s_est": round(tp[0] + tp[1] * stride, 1),
-                               "method": "16 head roots + 64 rank-stratified roots (stride %d), "
-                                         "sum = head + sample * stride" % stride}
+            r["plain_form"] = {"build_s_est": round(tp[0] + tp[1] * stride, 3),
+                               "method": "%d head roots + %d rank-stratified roots (stride %d), "
+                                         "sum = head + sample * stride" % (H, NS, stride)}
         out[nm] = r
         print("large:", nm, json.dumps(r), file=sys.stderr, flush=True)
         del d, pairs
@@ -232,7 +233,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form estimate")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--large", action="store_true",
-                    help="also build the two million-vertex workloads and report them in a 'large' object")
+                    help="also build the other workloads (64x64 grid, 1024x1024 diagonal grid, R-MAT 20) "
+                         "and report them in a 'large' object")
     ap.add_argument("--serve-full", action="store_true",
                     help="also run the full-size serving experiment (two resident labelings, 10^7 queries "
                          "at three rates, 16 builds); adds a 'serving_full' object")
