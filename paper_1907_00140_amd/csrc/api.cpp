@@ -611,12 +611,16 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64) {
         Timer tp(st);
         const int32_t gmax = std::min<int32_t>(o.prune_hubs > 0 ? o.prune_hubs : MAX_PREFIX, n / 2);
+        // prefix labels grouped by vertex, double-buffered: each level's
+        // labels extend the groups of the levels before it
         int32_t* pcount = A.get<int32_t>(n);
         int32_t* pfill = A.get<int32_t>(n);
-        int64_t* poff = A.get<int64_t>((size_t)n + 1);
+        int64_t* poff[2] = {A.get<int64_t>((size_t)n + 1), A.get<int64_t>((size_t)n + 1)};
         if (A.oom) return CHL_ERR_OOM;
-        uint64_t* plab = nullptr;
-        size_t plab_cap = 0;
+        uint64_t* plab[2] = {nullptr, nullptr};
+        size_t plab_cap[2] = {0, 0};
+        int cur = -1;                       // buffer holding the groups so far
+        unsigned long long grouped = 0;     // pool entries grouped so far
         // trees in flight and workgroup size of the levels: 512 and 1024
         // unless the caller fixed them (a caller that shares the device, such
         // as the server, caps both)
@@ -628,15 +632,20 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
         auto regroup = [&]() -> int {
             const unsigned long long used = B.last_used;
-            if (used > plab_cap) {
-                if (plab) A.drop(plab);
-                plab_cap = std::max<size_t>(used, 2 * plab_cap);
-                plab = A.get<uint64_t>(plab_cap);
-                if (!plab) return CHL_ERR_OOM;
+            const int nx = cur < 0 ? 0 : 1 - cur;
+            if (used > plab_cap[nx]) {
+                if (plab[nx]) A.drop(plab[nx]);
+                plab_cap[nx] = std::max<size_t>(used, 2 * plab_cap[nx]);
+                plab[nx] = A.get<uint64_t>(plab_cap[nx]);
+                if (!plab[nx]) return CHL_ERR_OOM;
             }
-            if (launch_prefix_labels(n, B.pool, used, pcount, poff, pfill, plab, scan_tmp, st)) return CHL_ERR_HIP;
-            B.poff = poff;
-            B.plab = plab;
+            if (launch_prefix_extend(n, B.pool, grouped, used, pcount, cur < 0 ? nullptr : poff[cur],
+                                     cur < 0 ? nullptr : plab[cur], poff[nx], plab[nx], pfill, scan_tmp, st))
+                return CHL_ERR_HIP;
+            cur = nx;
+            grouped = used;
+            B.poff = poff[cur];
+            B.plab = plab[cur];
             B.cursor_base = used;
             return 0;
         };

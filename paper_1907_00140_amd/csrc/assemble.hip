@@ -105,16 +105,40 @@ int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
-                         int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st) {
-    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, count, (int64_t)n);
-    hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, fill, (int64_t)n);
-    if (used > 0)
-        hipLaunchKernelGGL(k_count, dim3(g(used)), dim3(256), 0, st, pool.v, used, (const int32_t*)nullptr, count);
-    if (launch_scan_i32_to_i64(count, offsets, n, scan_temp, st)) return -1;
-    if (used > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(g(used)), dim3(256), 0, st, pool.v, pool.hub, pool.dist, used,
-                           (const int32_t*)nullptr, offsets, fill, lab);
+// fill[v] = size of v's old group (0 without old groups)
+__global__ void k_old_sizes(int32_t n, const int64_t* __restrict__ off_old, int32_t* __restrict__ fill) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        fill[v] = off_old ? (int32_t)(off_old[v + 1] - off_old[v]) : 0;
+}
+
+// one wave per vertex: its old group to the front of its new group
+__global__ void k_move_groups(int32_t n, const int64_t* __restrict__ off_old, const uint64_t* __restrict__ lab_old,
+                              const int64_t* __restrict__ off_new, uint64_t* __restrict__ lab_new) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < n; v += nwaves) {
+        const int64_t b = off_old[v], e = off_old[v + 1], o = off_new[v];
+        for (int64_t i = b + lane; i < e; i += 64) lab_new[o + (i - b)] = lab_old[i];
+    }
+}
+
+int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
+                         const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
+                         int32_t* fill, void* scan_temp, hipStream_t st) {
+    if (!off_old) hipLaunchKernelGGL(k_zero32, dim3(g(n)), dim3(256), 0, st, count, (int64_t)n);
+    const uint64_t add = used - from;
+    if (add > 0)
+        hipLaunchKernelGGL(k_count, dim3(g(add)), dim3(256), 0, st, pool.v + from, add, (const int32_t*)nullptr,
+                           count);
+    if (launch_scan_i32_to_i64(count, off_new, n, scan_temp, st)) return -1;
+    hipLaunchKernelGGL(k_old_sizes, dim3(g(n)), dim3(256), 0, st, n, off_old, fill);
+    if (off_old)
+        hipLaunchKernelGGL(k_move_groups, dim3(g((uint64_t)n * 64)), dim3(256), 0, st, n, off_old, lab_old, off_new,
+                           lab_new);
+    if (add > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(g(add)), dim3(256), 0, st, pool.v + from, pool.hub + from,
+                           pool.dist + from, add, (const int32_t*)nullptr, off_new, fill, lab_new);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

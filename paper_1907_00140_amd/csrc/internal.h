@@ -140,11 +140,15 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
                     int32_t* hub_pos, int32_t* dist, void* scan_temp, void* sort_temp,
                     hipStream_t st);
 
-// assemble.hip: labels of the pool entries [0, used) grouped by vertex
-// (rank position), as (hub << 32) | dist words; the pruning test takes a
-// minimum over a vertex's entries, so their order within a vertex is free
-int launch_prefix_labels(int32_t n, const Pool& pool, uint64_t used, int32_t* count, int64_t* offsets,
-                         int32_t* fill, uint64_t* lab, void* scan_temp, hipStream_t st);
+// assemble.hip: the labels of the pool entries [0, used) grouped by vertex
+// (rank position), as (hub << 32) | dist words, from the groups of the
+// entries [0, from) (off_old / lab_old; NULL when from == 0) and the entries
+// [from, used); count holds the running group sizes (cleared when from == 0).
+// The pruning test takes a minimum over a vertex's entries, so their order
+// within a group is free.
+int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
+                         const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
+                         int32_t* fill, void* scan_temp, hipStream_t st);
 // assemble.hip: totals of the per-root statistics (settled, arcs, stopped
 // early) into sums[0..2] (zeroed by the caller)
 int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);
