@@ -203,6 +203,18 @@ def large_workloads(chl, gg, stream):
              "phases_ms": {"prep": round(st["prep_ms"], 1), "prefix": round(st["prefix_ms"], 1),
                            "main": round(st["tree_ms"], 1), "assemble": round(st["assemble_ms"], 1)},
              "queries_per_s": round(qs, 1)}
+        wc = json.load(open(COUNTS)).get(nm, {})
+        if "arcs" in wc:
+            r["gteps"] = round(wc["arcs"] / min(times) / 1e9, 4)
+            r["oracle_arcs_unpruned"] = wc["arcs"]
+        lv = next((v for v in wc.values() if isinstance(v, dict) and v.get("grown") == st["prefix_roots"]
+                   and v.get("pmain") == st["prune_hubs"]), None)
+        if lv is not None:
+            a = lv["head"]["arcs"] + lv["rest"]["arcs"]
+            r["method_gteps"] = round(a / min(times) / 1e9, 4)
+            r["work_inflation"] = round(st["arcs"] / a, 3)
+        elif st["prune_hubs"] == 0 and "arcs" in wc:
+            r["work_inflation"] = round(st["arcs"] / wc["arcs"], 3)
         if nm.startswith("grid"):
             n = c["n"]
             H, NS = (64, 256) if n < 100_000 else (16, 64)

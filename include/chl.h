@@ -118,17 +118,19 @@ typedef struct chl_build_opts {
     int32_t root_stride;     /* >= 1 when root_count > 0 */
     int32_t prune_hubs;      /* batched form: rank-prefix pruning (Section 4.3).
                                 The trees of roots [0, 16) grow first; each
-                                later level of roots [g, 8g) is pruned by the
-                                labels of the hubs [0, g) (complete by then),
-                                up to a prefix of prune_hubs hubs (<= 4096);
-                                every other tree is pruned by that prefix. A
-                                relaxation is dropped when a walk through a
-                                prefix hub is no longer. Same labels either
-                                way. > 0: that prefix size; 0: 4096, kept only
-                                if the 16-hub level speeds up a probe of later
-                                trees (decided once per graph and ranking and
-                                cached; always kept when autotune is 0); < 0:
-                                off. Ignored by the plain form. */
+                                later level of roots [g, 8g) -- [g, 2g) after a
+                                level whose roots emitted >= 2^21 labels -- is
+                                pruned by the labels of the hubs [0, g)
+                                (complete by then), up to a prefix of
+                                prune_hubs hubs (<= 4096); every other tree is
+                                pruned by that prefix. A relaxation is dropped
+                                when a walk through a prefix hub is no longer.
+                                Same labels either way. > 0: that prefix size;
+                                0: min(4096, max(64, n/64)), kept only if the
+                                16-hub level halves the work of a probe of
+                                later trees (decided once per graph and
+                                ranking, cached; always kept when autotune is
+                                0); < 0: off. Ignored by the plain form. */
     int32_t team_wgs;        /* batched form: workgroups per tree for the levels
                                 of rank-prefix pruning that hold fewer trees than
                                 the device holds workgroups (the first, largest

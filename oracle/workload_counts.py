@@ -56,8 +56,9 @@ def counts(name, threads=None, pruned_only=False, levels=True):
     phase / main phase) of each configuration the library's batched build
     can run: no pruning ("unpruned"), the 16 unpruned probe-level roots
     followed by unpruned trees ("split16"), and pruning in the levels of
-    level_bounds() up to 4096 (or n/2) with the main phase pruned by that
-    whole prefix ("levels4096")."""
+    level_bounds() up to the build's default prefix, min(4096, max(64, n/64),
+    n/2) hubs, with the main phase pruned by that whole prefix
+    ("levels<prefix>")."""
     c = gg.make_config(name)
     n = int(c["n"])
     out = {"n": n, "m": int(c["m"]), "threads": threads or min(16, os.cpu_count() or 1)}
@@ -69,7 +70,7 @@ def counts(name, threads=None, pruned_only=False, levels=True):
         st = lab.stats
         out.update(_sums(st, 0, n))
         out["split16"] = {"grown": 16, "pmain": 0, "head": _sums(st, 0, 16), "rest": _sums(st, 16, n)}
-    gmax = min(LEVELS[-1], n // 2)
+    gmax = min(LEVELS[-1], max(64, n // 64), n // 2)
     lv = [g for g in LEVELS if g < gmax] + [gmax]
     if lv and levels:
         t = time.time()
