@@ -608,7 +608,15 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     double prune_ms = 0;
     int32_t grown = 0;
     const double wm = 0.5 * (1.0 + B.maxw);
-    if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64) {
+    // a graph on which the probe already found pruning not to pay skips the
+    // levels: its first roots simply start the main phase
+    bool known_unpruned = false;
+    if (o.prune_hubs == 0 && o.autotune) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_prune_keep.find(TuneKey{n, B.m, B.maxw, -1, B.sig});
+        known_unpruned = it != g_prune_keep.end() && !it->second;
+    }
+    if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64 && !known_unpruned) {
         Timer tp(st);
         // default prefix: n/64 hubs, at least 64, at most 4096: each level
         // adds latency, each prefix hub saves work in every later tree, and
@@ -891,7 +899,9 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     }
     bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta);
     if (!need) return 0;
-    TuneKey key{n, B.m, B.maxw, (o.mode * 8192 + B.grown) * 8192 + B.pbound, B.sig};
+    // (unpruned builds share one entry whether or not their first roots ran
+    // as a level)
+    TuneKey key{n, B.m, B.maxw, (o.mode * 8192 + (B.pbound ? B.grown : 0)) * 8192 + B.pbound, B.sig};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
