@@ -318,9 +318,10 @@ def main():
     gteps = A / b_s / 1e9
     qps = q / (float(np.median(query_ms)) / 1e3)
 
-    # roofline of the dominant kernel, the batched tree kernel: all its
-    # production launches of one build (the prefix levels and the main
-    # phase), timed with events on the build stream inside the library.
+    # roofline of the dominant kernels, the tree kernels (teams for the first
+    # levels, the batched kernel for the others and the main phase): every
+    # production launch of one build, timed with events on the build stream
+    # inside the library.
     # Algorithmic bytes = 16 per scanned arc + 16 per settled vertex + 8 per
     # label, with the units counted by the oracle's trees under the same
     # pruning configuration (tests/golden/workload_counts.json)
@@ -329,8 +330,11 @@ def main():
         cfg = None
         units = {"arcs": A, "settled": S, "labels": Lc}
     else:
-        cfg = next(v for k, v in counts.items() if isinstance(v, dict) and v.get("grown") == g
-                   and v.get("pmain") == pm)
+        cfg = next((v for k, v in counts.items() if isinstance(v, dict) and v.get("grown") == g
+                    and v.get("pmain") == pm), None)
+        if cfg is None:
+            sys.exit("no oracle work counts for a %d-hub prefix grown over %d roots: run "
+                     "python -m oracle.workload_counts %s" % (pm, g, WORKLOAD))
         units = {k: cfg["head"][k] + cfg["rest"][k] for k in ("arcs", "settled", "labels")}
     nl = max(1, int(np.median(klaunch)))
     alg_bytes = (16 * units["arcs"] + 16 * units["settled"] + 8 * units["labels"]) / nl
@@ -343,7 +347,7 @@ def main():
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "k_tree_batched (production launches: prefix levels + main phase)",
+                "kernel": "tree kernels k_tree_team + k_tree_batched (every production launch of a build: team levels, wide levels, main phase)",
                 "kernel_ms": round(per_launch_ms, 3), "launches_per_build": nl,
                 "alg_bytes_per_launch": alg_bytes,
                 "units_per_build": units}

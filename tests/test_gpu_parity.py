@@ -123,6 +123,21 @@ def test_team_grid():
         assert_same_labels(off, hub, dist, ref)
 
 
+def test_default_schedule_rmat14():
+    """Default pruning on a 16,384-vertex R-MAT graph: a max(64, n/64) = 256-hub
+    prefix grown in levels [0,16), [16,128), [128,256) (each level emits far
+    fewer than 2^21 labels, so the prefix grows 8x), then the main phase:
+    four production launches, and the oracle's labels."""
+    c = gg.make_config("rmat14s11")
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    _say("default schedule")
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], autotune=False)
+    assert_same_labels(off, hub, dist, ref)
+    st = L.stats()
+    assert st["prefix_roots"] == 256 and st["prune_hubs"] == 256
+    assert st["kernel_launches"] == 4
+
+
 def test_repeatable_rmat14():
     """Repeated builds give identical labels (no order-dependent races)."""
     c = gg.make_config("rmat14s11")

@@ -164,3 +164,16 @@ def test_levels_equal_definition(lib, seed):
     for levels, pmain in (([2, 8], 8), ([1, 4, 16], 16), ([3, 9, 27], 9), ([4, 16], 0)):
         lab = oracle.chl_pruned(row, col, w, order, levels=levels, pmain=pmain, threads=2, lib=lib)
         assert pins.oracle_labels(lab) == want, (levels, pmain)
+
+
+def test_level_schedule_rule():
+    """The pruning-level schedule the work counts use: roots [0, 16) first,
+    then a prefix 2x larger after a level whose roots emitted >= 2^21 labels,
+    else 8x larger, capped at the prefix size."""
+    from oracle.workload_counts import level_bounds
+    lab = np.zeros(70_000, np.int64)
+    lab[:16] = 200_000          # 3.2 M labels: work-bound level -> x2
+    lab[16:32] = 100_000        # 1.6 M labels -> x8
+    assert level_bounds(lab, 4096) == [16, 32, 256, 2048, 4096]
+    assert level_bounds(np.zeros(100, np.int64), 50) == [16, 50]
+    assert level_bounds(np.zeros(100, np.int64), 8) == [8]
