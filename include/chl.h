@@ -99,8 +99,9 @@ typedef struct chl_build_opts {
     int32_t roots_in_flight; /* batched: trees in flight (= workgroups) of the
                                 main phase, and at most that many (<= 512) in
                                 the pruning levels; 0 = tuned (levels: 512) */
-    int32_t wg_size;         /* 256, 512 or 1024 threads, also for the pruning
-                                levels; 0 = tuned (levels: 1024) */
+    int32_t wg_size;         /* 64, 128, 256, 512 or 1024 threads (plain form:
+                                256 or 512), also for the pruning levels;
+                                0 = tuned (levels: 1024) */
     int64_t delta;           /* bucket width of the delta-stepping frontier; 0 = tuned */
     int32_t early_term;      /* 1: stop a tree once no queued vertex is clean
                                 (Section 4.2, early termination); 0: grow every

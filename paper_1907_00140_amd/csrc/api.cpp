@@ -514,7 +514,10 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     chl_build_opts_default(&o);
     if (opts_in) o = *opts_in;
     if (o.mode != CHL_MODE_BATCHED && o.mode != CHL_MODE_PLAIN) return CHL_ERR_INVALID_ARG;
-    if (o.wg_size != 0 && o.wg_size != 256 && o.wg_size != 512 && o.wg_size != 1024) return CHL_ERR_INVALID_ARG;
+    if (o.wg_size != 0 && o.wg_size != 64 && o.wg_size != 128 && o.wg_size != 256 && o.wg_size != 512 &&
+        o.wg_size != 1024)
+        return CHL_ERR_INVALID_ARG;
+    if (o.mode == CHL_MODE_PLAIN && o.wg_size != 0 && o.wg_size != 256 && o.wg_size != 512) return CHL_ERR_INVALID_ARG;
     if (o.mode == CHL_MODE_PLAIN && o.wg_size == 1024) return CHL_ERR_INVALID_ARG;
     if (o.roots_in_flight < 0 || o.delta < 0) return CHL_ERR_INVALID_ARG;
     if (o.root_count < 0) return CHL_ERR_INVALID_ARG;
@@ -985,7 +988,9 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     // then workgroup size x threads in flight (trees in flight = threads /
     // workgroup size) at that bucket width
     {
-        const int wgs[3] = {256, 512, 1024};
+        // (64 and 128 threads: one or two waves per tree, for graphs whose
+        // main-phase trees are tiny)
+        const int wgs[5] = {64, 128, 256, 512, 1024};
         for (int w : wgs) {
             if (o.wg_size && w != wg) continue;
             if (o.roots_in_flight) {

@@ -1074,10 +1074,14 @@ int plain_grid_t() {
 
 int launch_tree_batched(const TreeParams& p, int key_bits, int wg, int phase, hipStream_t st) {
     if (key_bits == 32) {
+        if (wg == 64) return launch_batched_t<uint32_t, 64>(p, phase, st);
+        if (wg == 128) return launch_batched_t<uint32_t, 128>(p, phase, st);
         if (wg == 256) return launch_batched_t<uint32_t, 256>(p, phase, st);
         if (wg == 512) return launch_batched_t<uint32_t, 512>(p, phase, st);
         if (wg == 1024) return launch_batched_t<uint32_t, 1024>(p, phase, st);
     } else {
+        if (wg == 64) return launch_batched_t<uint64_t, 64>(p, phase, st);
+        if (wg == 128) return launch_batched_t<uint64_t, 128>(p, phase, st);
         if (wg == 256) return launch_batched_t<uint64_t, 256>(p, phase, st);
         if (wg == 512) return launch_batched_t<uint64_t, 512>(p, phase, st);
         if (wg == 1024) return launch_batched_t<uint64_t, 1024>(p, phase, st);
