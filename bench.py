@@ -403,8 +403,15 @@ def main():
         lab = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"], mode=oracle.MODE_PLANT, threads=threads)
         ct = time.perf_counter() - tc
         assert lab.total == Lc
+        tq = time.perf_counter()
+        qo = oracle.query(lab, c["pairs"])
+        tq = time.perf_counter() - tq
+        assert np.array_equal(qo, qout.cpu().numpy())
+        model = next((l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")), "?")
         cpu = {"value": round(A / ct / 1e9, 4), "unit": "GTEPS", "cores": threads, "kind": "oracle",
-               "sample": "full R-MAT scale-16 labeling (all 65,536 roots), %.1f s" % ct}
+               "sample": "full R-MAT scale-16 labeling (all 65,536 roots), %.1f s" % ct,
+               "queries_per_s_1_thread": round(len(c["pairs"]) / tq, 1),
+               "host": {"cpu": model, "nproc": os.cpu_count()}}
 
     out = {
         "metric": "CHL build time (s) + GTEPS; PPSD queries/s with p50/p99 latency, 1 MI355X",

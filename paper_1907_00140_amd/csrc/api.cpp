@@ -103,18 +103,40 @@ struct Timer {
 
 // Small device-to-host readbacks (control words, error flags, samples) go
 // through pinned host memory, so that several of them queue on the stream
-// and complete with one synchronisation. One block per host thread, kept
-// until the process ends.
+// and complete with one synchronisation. Each host thread holds one block
+// while it lives and hands it back to a process-wide free list when it ends,
+// so that threads that come and go (the server's build workers) reuse blocks
+// instead of allocating pinned memory, which can stall the device.
 struct HostCtl {
     int32_t c32[16];
     unsigned long long c64[4];
     int64_t smp[64];
     int64_t sums[4];
 };
+std::mutex g_hc_mu;
+std::vector<HostCtl*> g_hc_free;
+struct HostCtlLease {
+    HostCtl* h = nullptr;
+    ~HostCtlLease() {
+        if (!h) return;
+        std::lock_guard<std::mutex> lk(g_hc_mu);
+        g_hc_free.push_back(h);
+    }
+};
 HostCtl* host_ctl() {
-    static thread_local HostCtl* h = nullptr;
-    if (!h && hipHostMalloc((void**)&h, sizeof(HostCtl), hipHostMallocDefault) != hipSuccess) h = nullptr;
-    return h;
+    static thread_local HostCtlLease lease;
+    if (!lease.h) {
+        {
+            std::lock_guard<std::mutex> lk(g_hc_mu);
+            if (!g_hc_free.empty()) {
+                lease.h = g_hc_free.back();
+                g_hc_free.pop_back();
+            }
+        }
+        if (!lease.h && hipHostMalloc((void**)&lease.h, sizeof(HostCtl), hipHostMallocDefault) != hipSuccess)
+            lease.h = nullptr;
+    }
+    return lease.h;
 }
 
 // ---------------------------------------------------------------- tuning

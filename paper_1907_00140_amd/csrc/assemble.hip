@@ -49,7 +49,7 @@ __global__ void k_split(const uint64_t* __restrict__ tmp, uint64_t total, int32_
 int g(uint64_t work) {
     uint64_t b = (work + 255) / 256;
     if (b < 1) b = 1;
-    if (b > 65536) b = 65536;
+    if (b > 4096) b = 4096;   // grid-stride: 16 blocks per CU saturate HBM and leave room for other streams
     return (int)b;
 }
 

@@ -122,7 +122,7 @@ __global__ void k_sym(int32_t n, int64_t m, const int64_t* __restrict__ rrow, co
 int grid_for(int64_t work, int block) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
-    if (g > 65536) g = 65536;
+    if (g > 4096) g = 4096;   // grid-stride kernels: 16 blocks per CU
     return (int)g;
 }
 

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(BLK) void k_sort_global(uint64_t* __restrict__ keys
 
 int grid_cap(int64_t work) {
     int64_t g = work < 1 ? 1 : work;
-    return (int)(g > 65536 ? 65536 : g);
+    return (int)(g > 4096 ? 4096 : g);   // grid-stride kernels
 }
 
 }  // namespace

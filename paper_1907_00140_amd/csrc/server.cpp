@@ -293,6 +293,18 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
         return CHL_ERR_INVALID_ARG;
     auto* s = new chl_server();
     s->o = so;
+    // builds allocate from the device's default stream-ordered pool: let it
+    // keep up to the build budget instead of returning memory to the driver
+    // at every synchronisation (a fresh driver allocation can stall the
+    // device, and with it the query batches)
+    {
+        int dev = 0;
+        hipMemPool_t pool;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t keep = so.mem_budget;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        }
+    }
     bool ok = hipStreamCreateWithFlags(&s->qs, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; i < so.build_streams && ok; i++) {
         hipStream_t st;
