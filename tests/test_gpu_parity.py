@@ -81,7 +81,8 @@ def test_grid64_full():
 
 @pytest.mark.parametrize("k,wg,delta,eta,team", [(1, 256, 1, -1, 0), (3, 512, 7, 16, 1), (64, 1024, 50, 64, 2),
                                                  (256, 256, 100, 4, 16), (1024, 512, 400, 32, 5),
-                                                 (2048, 256, 10_000, -1, 0)])
+                                                 (2048, 256, 10_000, -1, 0), (4096, 64, 300, 64, 0),
+                                                 (1536, 128, 25, 16, 0)])
 def test_parameter_invariance_rmat12(k, wg, delta, eta, team):
     """Every (roots in flight, workgroup size, bucket width, pruning hubs,
     workgroups per tree of the first levels) gives the same labels."""
@@ -191,6 +192,12 @@ def test_invalid_inputs():
         with pytest.raises(chl.ChlError) as e:
             chl.build(r, c_, ww, o)
         assert e.value.code == -1
+    # options out of range
+    for kw in (dict(wg_size=96), dict(mode="plain", wg_size=64), dict(mode="plain", wg_size=1024),
+               dict(team_wgs=17), dict(team_wgs=-1), dict(prune_hubs=5000), dict(roots_in_flight=-2)):
+        with pytest.raises(chl.ChlError) as e:
+            chl.build(row, col, w, order, **kw)
+        assert e.value.code == -1, kw
     L = chl.build(row, col, w, order)
     with pytest.raises(chl.ChlError):
         L.query(np.array([[0, 4]], np.int32))
