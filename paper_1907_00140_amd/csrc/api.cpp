@@ -1,7 +1,8 @@
 // Host runtime behind the C-ABI of include/chl.h: argument checks, device
-// validation and rank renumbering, the two tree drivers (batched persistent
-// kernel, plain one-root-per-launch), growth of the label pool, label
-// assembly, queries, statistics and the autotuner.
+// validation and rank renumbering, the build schedule (rank-prefix pruning
+// levels, grown by teams of workgroups or by the batched persistent kernel,
+// then the main phase; or the plain one-root-per-launch form), growth of the
+// label pool, label assembly, queries, statistics and the autotuner.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -151,9 +152,8 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int k, wg;
-    int64_t delta;
-    int32_t eta;
+    int k, wg;          // trees in flight, workgroup size
+    int64_t delta;      // bucket width
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -624,10 +624,11 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
 
     // ---- rank-prefix pruning (Section 4.3) in levels: the trees of roots
-    //      [0, 16) grow unpruned; then every level [g, 4g) is pruned by the
-    //      labels of the hubs [0, g), which are complete, and so on up to the
-    //      prefix size; the main phase is pruned by the whole prefix. The
-    //      labels found so far are regrouped by vertex after every level.
+    //      [0, 16) grow unpruned; then every level [g, 8g) (or [g, 2g), see
+    //      LEVEL_LABELS_X2) is pruned by the labels of the hubs [0, g), which
+    //      are complete, and so on up to the prefix size; the main phase is
+    //      pruned by the whole prefix. The labels of every level extend the
+    //      per-vertex groups of the levels before it.
     int launches = 0;
     int prefix_launches = 0;
     double prune_ms = 0;
@@ -956,7 +957,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     B.stats = nullptr;              // probe runs leave no statistics
     auto t0 = std::chrono::steady_clock::now();
     double best = 1e30;
-    TuneVal bv{k, wg, delta, B.pbound};
+    TuneVal bv{k, wg, delta};
     int launches = 0;
     Slots s{};
     int kcur = 0;
@@ -983,7 +984,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
         double ms = 0;
         if (int r = time_once(kk, w, d, ms)) return r;
         seen[{kk, w, d}] = ms;
-        if (ms < best) { best = ms; bv = TuneVal{kk, w, d, B.pbound}; }
+        if (ms < best) { best = ms; bv = TuneVal{kk, w, d}; }
         return 0;
     };
     // coordinate search: bucket width (coarse, then refined), workgroup
@@ -1034,7 +1035,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             auto [kk, w, d] = rank[i].second;
             double ms = 0;
             if (int r = time_once(kk, w, d, ms)) return r;
-            if (rank[i].first + ms < best2) { best2 = rank[i].first + ms; bv = TuneVal{kk, w, d, B.pbound}; }
+            if (rank[i].first + ms < best2) { best2 = rank[i].first + ms; bv = TuneVal{kk, w, d}; }
         }
     }
     free_slots(A, s);

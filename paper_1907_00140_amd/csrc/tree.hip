@@ -32,8 +32,10 @@
 //
 // Batched form: a persistent kernel, one workgroup per tree; each workgroup
 // owns a slot of per-tree state and pops roots from a rank-ordered work queue
-// (the paper's atomic task counter, Section 3.1). Plain form: the whole grid
-// grows one tree per cooperative launch.
+// (the paper's atomic task counter, Section 3.1). Team form: the same queue,
+// one tree per team of workgroups, for launches with fewer trees than the
+// device holds workgroups. Plain form: the whole grid grows one tree per
+// cooperative launch.
 #include <hip/hip_cooperative_groups.h>
 
 #include "internal.h"
