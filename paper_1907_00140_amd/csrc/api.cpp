@@ -527,6 +527,180 @@ void chl_labels_free(chl_labels* h) {
 static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_opts& o,
                        hipStream_t st, int& k, int& wg, int64_t& delta, double& tune_ms);
 
+// The rank-prefix levels of a batched build (see chl_build_impl): grows the
+// trees of the roots [0, grown) and leaves their labels in the pool, the
+// prefix groups in B.poff / B.plab and B.pbound = prefix size (0 when the
+// probe drops pruning).
+static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tmp, hipStream_t st,
+                      int& launches, int32_t& grown) {
+    const int32_t n = B.n;
+    const double wm = 0.5 * (1.0 + B.maxw);
+    // default prefix: n/64 hubs, at least 64, at most 4096: each level
+    // adds latency, each prefix hub saves work in every later tree, and
+    // there are more later trees on larger graphs (R-MAT 16: 1024 hubs
+    // build 4% faster than 4096; R-MAT 20: 4096 run the main phase 2.8x
+    // faster than 2048)
+    const int32_t gdef = std::min<int32_t>(MAX_PREFIX, std::max<int32_t>(64, n / 64));
+    const int32_t gmax = std::min<int32_t>(o.prune_hubs > 0 ? o.prune_hubs : gdef, n / 2);
+    // prefix labels grouped by vertex, double-buffered: each level's
+    // labels extend the groups of the levels before it
+    int32_t* pcount = A.get<int32_t>(n);
+    int32_t* pfill = A.get<int32_t>(n);
+    int64_t* poff[2] = {A.get<int64_t>((size_t)n + 1), A.get<int64_t>((size_t)n + 1)};
+    if (A.oom) return CHL_ERR_OOM;
+    uint64_t* plab[2] = {nullptr, nullptr};
+    size_t plab_cap[2] = {0, 0};
+    int cur = -1;                       // buffer holding the groups so far
+    unsigned long long grouped = 0;     // pool entries grouped so far
+    // trees in flight and workgroup size of the levels: 512 and 1024
+    // unless the caller fixed them (a caller that shares the device, such
+    // as the server, caps both)
+    const int kcap = o.roots_in_flight > 0 ? std::min(512, o.roots_in_flight) : 512;
+    const int lwg = o.wg_size ? o.wg_size : 1024;
+    const int kpre = std::min(kcap, std::max(1, (int)(std::min<size_t>(4096, (size_t)(1ull << 33) / std::max<size_t>(1, slot_bytes(n, B.key_bits))))));
+    Slots s1{};
+    if (int r = alloc_slots(A, B, kpre, s1, st)) return r;
+    HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+    auto regroup = [&]() -> int {
+        const unsigned long long used = B.last_used;
+        const int nx = cur < 0 ? 0 : 1 - cur;
+        if (used > plab_cap[nx]) {
+            if (plab[nx]) A.drop(plab[nx]);
+            plab_cap[nx] = std::max<size_t>(used, 2 * plab_cap[nx]);
+            plab[nx] = A.get<uint64_t>(plab_cap[nx]);
+            if (!plab[nx]) return CHL_ERR_OOM;
+        }
+        if (launch_prefix_extend(n, B.pool, grouped, used, pcount, cur < 0 ? nullptr : poff[cur],
+                                 cur < 0 ? nullptr : plab[cur], poff[nx], plab[nx], pfill, scan_tmp, st))
+            return CHL_ERR_HIP;
+        cur = nx;
+        grouped = used;
+        B.poff = poff[cur];
+        B.plab = plab[cur];
+        B.cursor_base = used;
+        return 0;
+    };
+    // level 0
+    int32_t g = std::min<int32_t>(16, gmax);
+    // the first levels hold the largest trees: 1024-thread workgroups,
+    // teams of them for the narrow levels. Buckets of half the mean
+    // weight for the unpruned trees of level 0 (wider ones cost
+    // re-relaxation, narrower ones team barriers), twice the mean weight
+    // for the pruned levels, whose trees are smaller and latency bound
+    // (measured on R-MAT scales 16 and 20)
+    const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 2));
+    const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
+    // levels with fewer trees than the device holds workgroups of that
+    // size run as teams of workgroups, one tree per team
+    const int tcap = o.team_wgs == 1 || lwg < 512 ? 0 : team_capacity(B.key_bits, lwg);
+    auto team_shape = [&](int32_t nr, TeamCfg& tc) -> bool {
+        if (tcap < 2 || nr <= 0 || 2 * nr > tcap) return false;
+        tc.size = std::min(o.team_wgs ? o.team_wgs : 16, tcap / nr);
+        tc.nteams = std::min<int>(std::min<int>(nr, tcap / std::max(1, tc.size)), s1.k);
+        return tc.size >= 2;
+    };
+    // team buffers for the largest team launch of any level schedule
+    int tmax = 0;
+    for (int32_t f : {2, 8})
+        for (int32_t a = g, b = std::min<int32_t>(gmax, f * g); a < gmax; a = b, b = std::min<int32_t>(gmax, f * b)) {
+            TeamCfg tc;
+            if (team_shape(b - a, tc)) tmax = std::max(tmax, tc.nteams);
+        }
+    {
+        TeamCfg tc;
+        if (team_shape(g, tc)) tmax = std::max(tmax, tc.nteams);
+    }
+    int32_t* tfar2 = tmax ? A.get<int32_t>((size_t)tmax * n) : nullptr;
+    long long* tstate = tmax ? A.get<long long>((size_t)tmax * TEAM_WORDS) : nullptr;
+    if (A.oom) return CHL_ERR_OOM;
+    auto team_for = [&](int32_t nr, TeamCfg& tc) -> const TeamCfg* {
+        if (!team_shape(nr, tc) || tc.nteams > tmax) return nullptr;
+        tc.far2 = tfar2;
+        tc.tstate = tstate;
+        return &tc;
+    };
+    TeamCfg tc0;
+    if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
+                            team_for(g, tc0)))
+        return r;
+    if (int r = regroup()) return r;
+    unsigned long long level_labels = B.cursor_base;
+    grown = g;
+    bool probed = false;
+    bool keep = o.prune_hubs > 0 || !o.autotune;
+    const TuneKey pkey{n, B.m, B.maxw, -1, B.sig};
+    if (!keep) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_prune_keep.find(pkey);
+        if (it != g_prune_keep.end()) keep = it->second, probed = true;
+    }
+    if (!keep && !probed) {
+        // keep pruning only if the 16-hub prefix cuts the work of a
+        // rank-stratified sample of later trees at least in half (it does
+        // not on graphs whose top-ranked vertices cover few shortest
+        // paths, e.g. degree-ranked grids)
+        const int32_t p0 = std::min<int32_t>(gmax, n - 1), nprobe = std::min<int32_t>(128, n - p0);
+        std::vector<int32_t> probe;
+        for (int32_t i = 0; i < nprobe; i++) probe.push_back(p0 + (int32_t)((int64_t)(n - p0) * i / nprobe));
+        int64_t* sv = B.stats;
+        int64_t* tmp_stats = sv ? nullptr : A.get<int64_t>((size_t)n * STAT_COLS);
+        if (!sv && !tmp_stats) return CHL_ERR_OOM;
+        B.stats = sv ? sv : tmp_stats;
+        int64_t work[2] = {0, 0};
+        std::vector<int64_t> rows((size_t)n * STAT_COLS);
+        for (int on = 0; on < 2; on++) {
+            B.pbound = on ? g : 0;
+            HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+            if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, probe.data(), (int32_t)probe.size(), st,
+                                    &launches, 1))
+                return r;
+            HIPCHK(hipMemcpy(rows.data(), B.stats, rows.size() * 8, hipMemcpyDeviceToHost));
+            for (int32_t r : probe) work[on] += rows[(size_t)r * STAT_COLS + 1];
+        }
+        // the probe roots' statistics rows are written again by the main phase
+        if (!sv) A.drop(tmp_stats);
+        B.stats = sv;
+        HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+        keep = 2 * work[1] < work[0];
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_prune_keep[pkey] = keep;
+    }
+    B.pbound = 0;
+    if (keep) {
+        while (g < gmax) {
+            // a level whose trees emitted many labels did much work: grow
+            // the prefix by 2, so that the next level is pruned by more
+            // hubs; after a small level, whose time is the latency of its
+            // trees, grow by 8, to have fewer levels (the labels of a
+            // root do not depend on the schedule, so neither does the
+            // schedule itself)
+            const int32_t g2 = std::min<int32_t>(gmax, (level_labels >= LEVEL_LABELS_X2 ? 2 : 8) * g);
+            B.pbound = g;
+            TeamCfg tc;
+            const unsigned long long before = B.cursor_base;
+            if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
+                                    team_for(g2 - g, tc)))
+                return r;
+            if (int r = regroup()) return r;
+            level_labels = B.cursor_base - before;
+            g = g2;
+        }
+        grown = g;
+        B.pbound = g;
+    }
+    free_slots(A, s1);
+    if (tfar2) A.drop(tfar2);
+    if (tstate) A.drop(tstate);
+    B.grown = grown;
+    if (o.root_count > 0) {
+        // a root subset keeps only its own trees' labels
+        B.cursor_base = 0;
+        HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
+        if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
+    }
+    return 0;
+}
+
 static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
                           const chl_allocator* alloc_in, void* stream, chl_labels** out) {
     if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
@@ -633,7 +807,6 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     int prefix_launches = 0;
     double prune_ms = 0;
     int32_t grown = 0;
-    const double wm = 0.5 * (1.0 + B.maxw);
     // a graph on which the probe already found pruning not to pay skips the
     // levels: its first roots simply start the main phase
     bool known_unpruned = false;
@@ -644,170 +817,8 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     }
     if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64 && !known_unpruned) {
         Timer tp(st);
-        // default prefix: n/64 hubs, at least 64, at most 4096: each level
-        // adds latency, each prefix hub saves work in every later tree, and
-        // there are more later trees on larger graphs (R-MAT 16: 1024 hubs
-        // build 4% faster than 4096; R-MAT 20: 4096 run the main phase 2.8x
-        // faster than 2048)
-        const int32_t gdef = std::min<int32_t>(MAX_PREFIX, std::max<int32_t>(64, n / 64));
-        const int32_t gmax = std::min<int32_t>(o.prune_hubs > 0 ? o.prune_hubs : gdef, n / 2);
-        // prefix labels grouped by vertex, double-buffered: each level's
-        // labels extend the groups of the levels before it
-        int32_t* pcount = A.get<int32_t>(n);
-        int32_t* pfill = A.get<int32_t>(n);
-        int64_t* poff[2] = {A.get<int64_t>((size_t)n + 1), A.get<int64_t>((size_t)n + 1)};
-        if (A.oom) return CHL_ERR_OOM;
-        uint64_t* plab[2] = {nullptr, nullptr};
-        size_t plab_cap[2] = {0, 0};
-        int cur = -1;                       // buffer holding the groups so far
-        unsigned long long grouped = 0;     // pool entries grouped so far
-        // trees in flight and workgroup size of the levels: 512 and 1024
-        // unless the caller fixed them (a caller that shares the device, such
-        // as the server, caps both)
-        const int kcap = o.roots_in_flight > 0 ? std::min(512, o.roots_in_flight) : 512;
-        const int lwg = o.wg_size ? o.wg_size : 1024;
-        const int kpre = std::min(kcap, std::max(1, (int)(std::min<size_t>(4096, (size_t)(1ull << 33) / std::max<size_t>(1, slot_bytes(n, B.key_bits))))));
-        Slots s1{};
-        if (int r = alloc_slots(A, B, kpre, s1, st)) return r;
-        HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
-        auto regroup = [&]() -> int {
-            const unsigned long long used = B.last_used;
-            const int nx = cur < 0 ? 0 : 1 - cur;
-            if (used > plab_cap[nx]) {
-                if (plab[nx]) A.drop(plab[nx]);
-                plab_cap[nx] = std::max<size_t>(used, 2 * plab_cap[nx]);
-                plab[nx] = A.get<uint64_t>(plab_cap[nx]);
-                if (!plab[nx]) return CHL_ERR_OOM;
-            }
-            if (launch_prefix_extend(n, B.pool, grouped, used, pcount, cur < 0 ? nullptr : poff[cur],
-                                     cur < 0 ? nullptr : plab[cur], poff[nx], plab[nx], pfill, scan_tmp, st))
-                return CHL_ERR_HIP;
-            cur = nx;
-            grouped = used;
-            B.poff = poff[cur];
-            B.plab = plab[cur];
-            B.cursor_base = used;
-            return 0;
-        };
-        // level 0
-        int32_t g = std::min<int32_t>(16, gmax);
-        // the first levels hold the largest trees: 1024-thread workgroups,
-        // teams of them for the narrow levels. Buckets of half the mean
-        // weight for the unpruned trees of level 0 (wider ones cost
-        // re-relaxation, narrower ones team barriers), twice the mean weight
-        // for the pruned levels, whose trees are smaller and latency bound
-        // (measured on R-MAT scales 16 and 20)
-        const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 2));
-        const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
-        // levels with fewer trees than the device holds workgroups of that
-        // size run as teams of workgroups, one tree per team
-        const int tcap = o.team_wgs == 1 || lwg < 512 ? 0 : team_capacity(B.key_bits, lwg);
-        auto team_shape = [&](int32_t nr, TeamCfg& tc) -> bool {
-            if (tcap < 2 || nr <= 0 || 2 * nr > tcap) return false;
-            tc.size = std::min(o.team_wgs ? o.team_wgs : 16, tcap / nr);
-            tc.nteams = std::min<int>(std::min<int>(nr, tcap / std::max(1, tc.size)), s1.k);
-            return tc.size >= 2;
-        };
-        // team buffers for the largest team launch of any level schedule
-        int tmax = 0;
-        for (int32_t f : {2, 8})
-            for (int32_t a = g, b = std::min<int32_t>(gmax, f * g); a < gmax; a = b, b = std::min<int32_t>(gmax, f * b)) {
-                TeamCfg tc;
-                if (team_shape(b - a, tc)) tmax = std::max(tmax, tc.nteams);
-            }
-        {
-            TeamCfg tc;
-            if (team_shape(g, tc)) tmax = std::max(tmax, tc.nteams);
-        }
-        int32_t* tfar2 = tmax ? A.get<int32_t>((size_t)tmax * n) : nullptr;
-        long long* tstate = tmax ? A.get<long long>((size_t)tmax * TEAM_WORDS) : nullptr;
-        if (A.oom) return CHL_ERR_OOM;
-        auto team_for = [&](int32_t nr, TeamCfg& tc) -> const TeamCfg* {
-            if (!team_shape(nr, tc) || tc.nteams > tmax) return nullptr;
-            tc.far2 = tfar2;
-            tc.tstate = tstate;
-            return &tc;
-        };
-        TeamCfg tc0;
-        if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
-                                team_for(g, tc0)))
-            return r;
-        if (int r = regroup()) return r;
-        unsigned long long level_labels = B.cursor_base;
-        grown = g;
-        bool probed = false;
-        bool keep = o.prune_hubs > 0 || !o.autotune;
-        const TuneKey pkey{n, B.m, B.maxw, -1, B.sig};
-        if (!keep) {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_prune_keep.find(pkey);
-            if (it != g_prune_keep.end()) keep = it->second, probed = true;
-        }
-        if (!keep && !probed) {
-            // keep pruning only if the 16-hub prefix cuts the work of a
-            // rank-stratified sample of later trees at least in half (it does
-            // not on graphs whose top-ranked vertices cover few shortest
-            // paths, e.g. degree-ranked grids)
-            const int32_t p0 = std::min<int32_t>(gmax, n - 1), nprobe = std::min<int32_t>(128, n - p0);
-            std::vector<int32_t> probe;
-            for (int32_t i = 0; i < nprobe; i++) probe.push_back(p0 + (int32_t)((int64_t)(n - p0) * i / nprobe));
-            int64_t* sv = B.stats;
-            int64_t* tmp_stats = sv ? nullptr : A.get<int64_t>((size_t)n * STAT_COLS);
-            if (!sv && !tmp_stats) return CHL_ERR_OOM;
-            B.stats = sv ? sv : tmp_stats;
-            int64_t work[2] = {0, 0};
-            std::vector<int64_t> rows((size_t)n * STAT_COLS);
-            for (int on = 0; on < 2; on++) {
-                B.pbound = on ? g : 0;
-                HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
-                if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, probe.data(), (int32_t)probe.size(), st,
-                                        &launches, 1))
-                    return r;
-                HIPCHK(hipMemcpy(rows.data(), B.stats, rows.size() * 8, hipMemcpyDeviceToHost));
-                for (int32_t r : probe) work[on] += rows[(size_t)r * STAT_COLS + 1];
-            }
-            // the probe roots' statistics rows are written again by the main phase
-            if (!sv) A.drop(tmp_stats);
-            B.stats = sv;
-            HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
-            keep = 2 * work[1] < work[0];
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_prune_keep[pkey] = keep;
-        }
-        B.pbound = 0;
-        if (keep) {
-            while (g < gmax) {
-                // a level whose trees emitted many labels did much work: grow
-                // the prefix by 2, so that the next level is pruned by more
-                // hubs; after a small level, whose time is the latency of its
-                // trees, grow by 8, to have fewer levels (the labels of a
-                // root do not depend on the schedule, so neither does the
-                // schedule itself)
-                const int32_t g2 = std::min<int32_t>(gmax, (level_labels >= LEVEL_LABELS_X2 ? 2 : 8) * g);
-                B.pbound = g;
-                TeamCfg tc;
-                const unsigned long long before = B.cursor_base;
-                if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
-                                        team_for(g2 - g, tc)))
-                    return r;
-                if (int r = regroup()) return r;
-                level_labels = B.cursor_base - before;
-                g = g2;
-            }
-            grown = g;
-            B.pbound = g;
-        }
-        free_slots(A, s1);
-        if (tfar2) A.drop(tfar2);
-        if (tstate) A.drop(tstate);
+        if (int r = run_levels(A, B, o, scan_tmp, st, launches, grown)) return r;
         prefix_launches = launches;
-        B.grown = grown;
-        if (o.root_count > 0) {
-            // a root subset keeps only its own trees' labels
-            B.cursor_base = 0;
-            HIPCHK(hipMemsetAsync(B.ctl64, 0, 8, st));
-            if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
-        }
         prune_ms = tp.stop();
     }
 
