@@ -64,6 +64,8 @@ def load(path=None):
     lib.oracle_run_free.argtypes = [vp]
     lib.oracle_query.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
     lib.oracle_sssp.argtypes = [C.c_int32, vp, vp, vp, C.c_int32, vp]
+    lib.oracle_parents.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.oracle_paths.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, vp]
     if path is None:
         _lib = lib
     return lib
@@ -202,3 +204,45 @@ def sssp(row_ptr, col, w, src, lib=None):
     out = np.zeros(n, dtype=np.int64)
     lib.oracle_sssp(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data, int(src), out.ctypes.data)
     return out
+
+
+def parents(labels, row_ptr, col, w, lib=None):
+    """Per label of ``labels`` (same order): the parent vertex (input id; the
+    smallest-id neighbour that is the next vertex of a shortest path towards
+    the hub; -1 for a hub's own label) and the position of the parent's label
+    of the same hub within the parent's list. Returns (parent, slot) int32."""
+    lib = lib or load()
+    row_ptr, col, w, _ = _graph_args(row_ptr, col, w, np.zeros(1, np.int32))
+    off = np.ascontiguousarray(labels.offsets, dtype=np.int64)
+    hub = np.ascontiguousarray(labels.hub_pos, dtype=np.int32)
+    dist = np.ascontiguousarray(labels.dist, dtype=np.int64)
+    total = int(off[-1])
+    par = np.zeros(max(total, 1), dtype=np.int32)
+    slot = np.zeros(max(total, 1), dtype=np.int32)
+    lib.oracle_parents(len(off) - 1, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data, off.ctypes.data,
+                       hub.ctypes.data, dist.ctypes.data, par.ctypes.data, slot.ctypes.data)
+    return par[:total], slot[:total]
+
+
+def paths(labels, parent, slot, pairs, lib=None):
+    """Shortest paths for int32 pairs [q, 2]: (hops int64[q], -1 when
+    disconnected; path_off int64[q+1]; path int32[path_off[q]]), pair k's
+    vertices being path[path_off[k]:path_off[k+1]], u first, v last."""
+    lib = lib or load()
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    q = len(pairs)
+    off = np.ascontiguousarray(labels.offsets, dtype=np.int64)
+    hub = np.ascontiguousarray(labels.hub_pos, dtype=np.int32)
+    dist = np.ascontiguousarray(labels.dist, dtype=np.int64)
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    sl = np.ascontiguousarray(slot, dtype=np.int32)
+    hops = np.zeros(max(q, 1), dtype=np.int64)
+    lib.oracle_paths(off.ctypes.data, hub.ctypes.data, dist.ctypes.data, par.ctypes.data, sl.ctypes.data,
+                     pairs.ctypes.data, q, hops.ctypes.data, None, None)
+    hops = hops[:q]
+    path_off = np.zeros(q + 1, dtype=np.int64)
+    np.cumsum(np.where(hops >= 0, hops + 1, 0), out=path_off[1:])
+    path = np.zeros(max(int(path_off[-1]), 1), dtype=np.int32)
+    lib.oracle_paths(off.ctypes.data, hub.ctypes.data, dist.ctypes.data, par.ctypes.data, sl.ctypes.data,
+                     pairs.ctypes.data, q, hops.ctypes.data, path_off.ctypes.data, path.ctypes.data)
+    return hops, path_off, path[:int(path_off[-1])]

@@ -43,7 +43,9 @@
  * hub first (Algorithm 2's sort step; the query merge of Section 5 relies on
  * it). oracle_query() answers distance queries by the sorted-list merge of
  * Section 5 (QLSN): the minimum of d_u + d_v over common hubs, -1 when the
- * lists share no hub.
+ * lists share no hub. oracle_parents() and oracle_paths() add the
+ * shortest-path extension of Section 4.4: per label the next vertex towards
+ * its hub, and paths as two chains of parents joined at the common hub.
  */
 #include <pthread.h>
 #include <stdatomic.h>
@@ -563,4 +565,96 @@ void oracle_sssp(int32_t n, const int64_t* row_ptr, const int32_t* col,
     }
     for (int32_t v = 0; v < n; v++) if (out[v] == INF64) out[v] = -1;
     free(done); free(hp.a);
+}
+
+/* ---------------- shortest paths from the labels ----------------
+ * Keeping with each label (h, d(v,h)) of L_v the next vertex from v towards
+ * h turns the labeling into a shortest-path oracle (Section 4.4, last
+ * paragraph): the path u -> v through the common hub h is u's chain of
+ * parents down to h followed by the reverse of v's chain.
+ *
+ * Parent of (h, d) in L_v: a neighbour p of v with d(p,h) + w(p,v) = d(v,h),
+ * i.e. the next vertex of some shortest v-h path. Every such p holds the
+ * label (h, d(p,h)) itself: a shortest p-h path followed by the arc (p,v)
+ * is a shortest v-h path, so SP_{p,h} lies inside SP_{v,h}, whose highest
+ * ranked vertex is h. The paper leaves the choice among several such p
+ * open; the neighbour with the smallest input id is taken. slot = position
+ * of p's label (h, .) within L_p, so a walk takes one step per edge. The
+ * hub's own label (v = h, d = 0) has parent -1 (positive weights: no
+ * neighbour can reach h in 0 - w). */
+static int64_t find_hub(const int64_t* off, const int32_t* hub, int32_t x, int32_t h) {
+    int64_t lo = off[x], hi = off[x + 1];
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (hub[mid] < h) lo = mid + 1; else hi = mid;
+    }
+    return (lo < off[x + 1] && hub[lo] == h) ? lo : -1;
+}
+
+void oracle_parents(int32_t n, const int64_t* row_ptr, const int32_t* col, const int32_t* wt,
+                    const int64_t* off, const int32_t* hub, const int64_t* dist,
+                    int32_t* parent, int32_t* slot) {
+    for (int32_t v = 0; v < n; v++)
+        for (int64_t i = off[v]; i < off[v + 1]; i++) {
+            int32_t best = -1, bslot = -1;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; e++) {
+                int32_t p = col[e];
+                int64_t j = find_hub(off, hub, p, hub[i]);
+                if (j < 0 || dist[j] + wt[e] != dist[i]) continue;
+                if (best < 0 || p < best) { best = p; bslot = (int32_t)(j - off[p]); }
+            }
+            parent[i] = best;
+            slot[i] = bslot;
+        }
+}
+
+/* Follow the parents from label index i of vertex x down to the hub; writes
+ * the vertices (x first) to out when out != NULL; returns the edge count. */
+static int64_t walk(const int64_t* off, const int32_t* parent, const int32_t* slot,
+                    int32_t x, int64_t i, int32_t* out) {
+    int64_t k = 0;
+    if (out) out[0] = x;
+    while (parent[i] >= 0) {
+        int32_t p = parent[i];
+        i = off[p] + slot[i];
+        x = p;
+        k++;
+        if (out) out[k] = x;
+    }
+    return k;
+}
+
+/* Path queries. The hub is the common hub with the smallest d_u + d_v and,
+ * among equal sums, the most important one (smallest rank position): the
+ * highest ranked vertex of SP_{u,v}. hops[k] = number of edges, -1 when the
+ * two lists share no hub. With path != NULL, the hops[k] + 1 vertices of
+ * pair k, u first and v last, go to path[path_off[k] ...]. */
+void oracle_paths(const int64_t* off, const int32_t* hub, const int64_t* dist,
+                  const int32_t* parent, const int32_t* slot, const int32_t* pairs, int64_t q,
+                  int64_t* hops, const int64_t* path_off, int32_t* path) {
+    for (int64_t k = 0; k < q; k++) {
+        int32_t u = pairs[2 * k], v = pairs[2 * k + 1];
+        int64_t i = off[u], ie = off[u + 1], j = off[v], je = off[v + 1];
+        int64_t best = -1, bi = -1, bj = -1;
+        while (i < ie && j < je) {
+            if (hub[i] < hub[j]) i++;
+            else if (hub[i] > hub[j]) j++;
+            else {
+                int64_t s = dist[i] + dist[j];
+                if (best < 0 || s < best) { best = s; bi = i; bj = j; }
+                i++; j++;
+            }
+        }
+        if (best < 0) { hops[k] = -1; continue; }
+        int64_t hu = walk(off, parent, slot, u, bi, NULL);
+        int64_t hv = walk(off, parent, slot, v, bj, NULL);
+        hops[k] = hu + hv;
+        if (!path) continue;
+        int32_t* o = path + path_off[k];
+        walk(off, parent, slot, u, bi, o);
+        int32_t* tmp = (int32_t*)malloc((size_t)(hv + 1) * sizeof(int32_t));
+        walk(off, parent, slot, v, bj, tmp);
+        for (int64_t t = 0; t < hv; t++) o[hu + 1 + t] = tmp[hv - 1 - t];
+        free(tmp);
+    }
 }

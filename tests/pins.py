@@ -392,6 +392,102 @@ def check_pruned(lib, n, m, wmax, seed):
     assert oracle_labels(lab) == want
 
 
+# ---------------------------------------------------------------- shortest paths
+def sp_parent(D, row, col, w, h, v):
+    """Smallest-id neighbour p of v that is the next vertex of a shortest v-h
+    path (D[h][p] + w(p,v) = D[h][v]), from Floyd-Warshall distances; -1 if
+    none (v = h)."""
+    best = -1
+    for e in range(row[v], row[v + 1]):
+        p = int(col[e])
+        if D[h, p] < INF and D[h, p] + int(w[e]) == D[h, v] and (best < 0 or p < best):
+            best = p
+    return best
+
+
+def check_parent_labels(lab, par, slot, D, row, col, w, order):
+    """Every label's parent is the smallest-id shortest-path neighbour
+    towards its hub (Floyd-Warshall), and slot points at the parent's label
+    of the same hub, whose distance is D[h][parent]."""
+    off, hub, dist = lab.offsets, lab.hub_pos, lab.dist
+    for v in range(lab.n):
+        for i in range(off[v], off[v + 1]):
+            h = int(order[hub[i]])
+            want = sp_parent(D, row, col, w, h, v)
+            assert par[i] == want, (v, h, par[i], want)
+            if want < 0:
+                assert v == h and slot[i] == -1
+                continue
+            j = off[want] + slot[i]
+            assert off[want] <= j < off[want + 1]
+            assert hub[j] == hub[i] and dist[j] == D[h, want]
+
+
+def check_path_walks(paths, D, row, col, w, order):
+    """paths = (hops, path_off, path) for all n*n pairs in row-major order.
+    Connected pairs: the path starts at u, ends at v, follows arcs whose
+    weights sum to D[u][v], passes through h_m, the highest ranked vertex of
+    SP_{u,v}, and both halves step to the smallest-id shortest-path
+    neighbour towards h_m. Disconnected pairs: hops -1, no vertices."""
+    hops, poff, path = paths
+    n = len(D)
+    pos = pos_of(order)
+    wmin = {}
+    for v in range(n):
+        for e in range(row[v], row[v + 1]):
+            key = (v, int(col[e]))
+            wmin[key] = min(wmin.get(key, INF), int(w[e]))
+    for u in range(n):
+        for v in range(n):
+            k = u * n + v
+            P = path[poff[k]:poff[k + 1]].tolist()
+            if D[u, v] >= INF:
+                assert hops[k] == -1 and not P
+                continue
+            assert len(P) == hops[k] + 1 and P[0] == u and P[-1] == v
+            assert sum(wmin[(P[t], P[t + 1])] for t in range(len(P) - 1)) == D[u, v]
+            on = [x for x in range(n) if D[u, x] + D[x, v] == D[u, v]]
+            hm = min(on, key=lambda x: pos[x])
+            assert hm in P, (u, v, hm, P)
+            a = P.index(hm)
+            for half in (P[:a + 1], P[a:][::-1]):
+                for t in range(len(half) - 1):
+                    assert half[t + 1] == sp_parent(D, row, col, w, hm, half[t]), (u, v, half)
+
+
+def check_paths_bruteforce(lib, n, m, wmax, seed):
+    """Parents and all-pairs paths of a random multigraph with ties."""
+    g = np.random.default_rng(seed)
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = csr_from_edges(n, e)
+    order = gg.random_rank(n, seed)
+    D = floyd_warshall(n, row, col, w)
+    lab = oracle.chl(row, col, w, order, threads=2, lib=lib)
+    par, slot = oracle.parents(lab, row, col, w, lib=lib)
+    check_parent_labels(lab, par, slot, D, row, col, w, order)
+    uu, vv = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.int32)
+    check_path_walks(oracle.paths(lab, par, slot, pairs, lib=lib), D, row, col, w, order)
+
+
+def check_path_graph_walks(lib, n, seed):
+    """Path 0-1-...-(n-1): the shortest u-v path is the segment between them."""
+    g = np.random.default_rng(seed)
+    ws = g.integers(1, 10, n - 1)
+    row, col, w = csr_from_edges(n, [(i, i + 1, int(ws[i])) for i in range(n - 1)])
+    order = gg.random_rank(n, seed)
+    lab = oracle.chl(row, col, w, order, threads=2, lib=lib)
+    par, slot = oracle.parents(lab, row, col, w, lib=lib)
+    uu, vv = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.int32)
+    hops, poff, path = oracle.paths(lab, par, slot, pairs, lib=lib)
+    for k, (u, v) in enumerate(pairs.tolist()):
+        step = 1 if v >= u else -1
+        assert path[poff[k]:poff[k + 1]].tolist() == list(range(u, v + step, step))
+        assert hops[k] == abs(u - v)
+
+
 def run_all(lib):
     """Every pin, smallish; used against planted mistakes."""
     check_golden(lib, "fig1_example.txt")
@@ -410,3 +506,6 @@ def run_all(lib):
         check_stats(lib, 20, 34, 2, 200 + s)
     for s in range(4):
         check_pruned(lib, 26, 44, 3, 300 + s)
+    for s in range(4):
+        check_paths_bruteforce(lib, 22, 40, 2 + s % 2, 400 + s)
+    check_path_graph_walks(lib, 14, 8)

@@ -177,3 +177,43 @@ def test_level_schedule_rule():
     assert level_bounds(lab, 4096) == [16, 32, 256, 2048, 4096]
     assert level_bounds(np.zeros(100, np.int64), 50) == [16, 50]
     assert level_bounds(np.zeros(100, np.int64), 8) == [8]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_parents_and_paths_bruteforce(lib, seed):
+    pins.check_paths_bruteforce(lib, 20 + 3 * seed, 30 + 6 * seed, 1 + seed % 3, 500 + seed)
+
+
+def test_path_graph_walks(lib):
+    for s in range(3):
+        pins.check_path_graph_walks(lib, 15 + s, s)
+
+
+def test_parents_grid64_against_dijkstra(lib):
+    """grid64: for sampled hubs, every labelled vertex's parent is the
+    smallest-id neighbour p with d(h,p) + w = d(h,v) (Dijkstra from h), and
+    sampled paths are walks along arcs of the queried length."""
+    c = gg.make_config("grid64")
+    row, col, w, order = c["row_ptr"], c["col"], c["w"], c["order"]
+    lab = oracle.chl(row, col, w, order, lib=lib)
+    par, slot = oracle.parents(lab, row, col, w, lib=lib)
+    for hp in (0, 1, 7, 100, 2000, 4095):
+        h = int(order[hp])
+        dh = oracle.sssp(row, col, w, h, lib=lib)
+        vs = np.nonzero(np.diff(lab.offsets) > 0)[0]
+        for v in vs:
+            a, b = lab.offsets[v], lab.offsets[v + 1]
+            i = a + np.searchsorted(lab.hub_pos[a:b], hp)
+            if i == b or lab.hub_pos[i] != hp:
+                continue
+            nb = [(int(col[e]), int(w[e])) for e in range(row[v], row[v + 1])]
+            want = min((p for p, x in nb if dh[p] + x == dh[v]), default=-1)
+            assert par[i] == want
+    pairs = c["pairs"][:300]
+    hops, poff, path = oracle.paths(lab, par, slot, pairs, lib=lib)
+    d = oracle.query(lab, pairs, lib=lib)
+    wt = {(v, int(col[e])): int(w[e]) for v in range(len(row) - 1) for e in range(row[v], row[v + 1])}
+    for k, (u, v) in enumerate(pairs.tolist()):
+        P = path[poff[k]:poff[k + 1]].tolist()
+        assert P[0] == u and P[-1] == v and len(P) == hops[k] + 1
+        assert sum(wt[(P[t], P[t + 1])] for t in range(len(P) - 1)) == d[k]

@@ -41,6 +41,16 @@ MUTANTS = {
     # prefix label distances one too small: over-pruning
     "prefix_dist": ("P->dist[k] = ld[t][i];", "P->dist[k] = ld[t][i] - 1;"),
     # sssp: wrong weight index
+    # parent: largest-id shortest-path neighbour instead of the smallest
+    "parent_max": ("if (best < 0 || p < best) { best = p;", "if (best < 0 || p > best) { best = p;"),
+    # parent: any closer neighbour holding the hub taken as the next vertex
+    "parent_dist": ("if (j < 0 || dist[j] + wt[e] != dist[i]) continue;",
+                    "if (j < 0 || dist[j] >= dist[i]) continue;"),
+    # path: the least important hub among equal sums
+    "path_tie": ("if (best < 0 || s < best) { best = s; bi = i; bj = j; }",
+                 "if (best < 0 || s <= best) { best = s; bi = i; bj = j; }"),
+    # path: v's half not reversed
+    "path_reverse": ("o[hu + 1 + t] = tmp[hv - 1 - t];", "o[hu + 1 + t] = tmp[t];"),
     "sssp_w": ("int64_t nd = it.d + wt[e];\n            if (nd < out[col[e]])",
                "int64_t nd = it.d + wt[row_ptr[it.v]];\n            if (nd < out[col[e]])"),
 }
