@@ -180,6 +180,53 @@ int chl_labels_hub_vertex(const chl_labels* h, int32_t* hub_vertex, int to_host,
  * an id outside [0, n) gives CHL_ERR_INVALID_ARG (out is then unspecified). */
 int chl_query(const chl_labels* h, const int32_t* pairs, int64_t q, int64_t* out, void* stream);
 
+/* ---- shortest paths (Section 4.4, last paragraph: a label that also keeps
+ * the tree parent of its vertex answers path queries in time linear in the
+ * path's edge count) ----
+ * Parent of the label (h, d) of L_v: the neighbour p of v with the smallest
+ * input id such that d(p, h) + w(p, v) = d, i.e. the next vertex of a
+ * shortest v-h path (every such p holds a label of hub h); -1 for a hub's
+ * own label (v = h). slot: the position of p's label of hub h within L_p
+ * (-1 with parent -1).
+ *
+ * Compute the parents of every label of h: parent[total] and slot[total]
+ * (int32, device, caller-owned, in the label order of chl_labels_export).
+ * g must be the graph the labeling was built from (device CSR, input ids);
+ * g->n must equal the labeling's n. Synchronises `stream`. Errors:
+ * CHL_ERR_INVALID_ARG (NULL or mismatched arguments; an arc with a
+ * neighbour outside [0, n) or a weight < 1, or a malformed row; such arcs
+ * are skipped and the parents are then unspecified), CHL_ERR_HIP. */
+int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32_t* parent, int32_t* slot,
+                       void* stream);
+
+/* Path lengths for pairs[2q] (device int32 input ids, as for chl_query),
+ * with the parent and slot arrays of chl_labels_parents (device): hops[q]
+ * (device int64) = number of edges of the path from u to v, 0 when u == v,
+ * -1 when u and v are disconnected, -2 for an invalid pair. path_off
+ * (device int64[q+1], may be NULL) receives the exclusive prefix sum of the
+ * per-pair vertex counts (hops + 1, or 0 when disconnected), so path_off[q]
+ * is the size of the path array chl_query_paths fills. The path of a pair
+ * runs through the common hub h that gives d(u, v) (the most important one
+ * among equal sums, i.e. the highest ranked vertex of SP_{u,v}): u's chain
+ * of parents down to h, then the reverse of v's chain. Allocates q * 8 bytes
+ * plus scan scratch through the labeling's allocator when path_off is given.
+ * Synchronises `stream`. Errors: CHL_ERR_INVALID_ARG (an id outside
+ * [0, n), or parent/slot arrays that do not fit the labeling),
+ * CHL_ERR_OOM, CHL_ERR_HIP. */
+int chl_query_path_hops(const chl_labels* h, const int32_t* parent, const int32_t* slot,
+                        const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
+                        void* stream);
+
+/* Write the paths: the vertices (input ids, u first, v last) of pair k go
+ * to path[path_off[k] .. path_off[k+1]-1] (device int32, caller-owned,
+ * path_off[q] entries) for path_off as returned by chl_query_path_hops for
+ * the same pairs. A pair whose range does not hold exactly its hops + 1
+ * vertices gets CHL_ERR_INVALID_ARG; nothing is written outside a pair's
+ * range. Synchronises `stream`. */
+int chl_query_paths(const chl_labels* h, const int32_t* parent, const int32_t* slot,
+                    const int32_t* pairs, int64_t q, const int64_t* path_off, int32_t* path,
+                    void* stream);
+
 /* ---- statistics ---- */
 typedef struct chl_stats {
     int64_t n;               /* vertices (= roots) */

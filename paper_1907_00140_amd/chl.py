@@ -88,6 +88,9 @@ def load(path=LIB_PATH):
             "chl_labels_export": (C.c_int, [vp, vp, vp, vp, C.c_int, vp]),
             "chl_labels_hub_vertex": (C.c_int, [vp, vp, C.c_int, vp]),
             "chl_query": (C.c_int, [vp, vp, i64, vp, vp]),
+            "chl_labels_parents": (C.c_int, [vp, vp, vp, vp, vp]),
+            "chl_query_path_hops": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
+            "chl_query_paths": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "chl_build_stats": (C.c_int, [vp, vp, vp, C.c_int, vp]),
             "chl_labels_free": (None, [vp]),
             "chl_server_opts_default": (None, [vp]),
@@ -230,6 +233,48 @@ class Labels:
             out = torch.empty(max(q, 1), dtype=torch.int64, device="cuda")
         _check(self.lib.chl_query(self._h, p.data_ptr(), q, out.data_ptr(), _stream_ptr(stream)), "chl_query")
         return out[:q]
+
+    def parents(self, row_ptr, col, w, stream=None):
+        """Per label (export order): the next vertex towards its hub on a
+        shortest path (smallest input id among the candidates; -1 for a hub's
+        own label) and the position of that vertex's label of the same hub in
+        its list. g = the CSR the labeling was built from. Returns (parent,
+        slot) int32 device tensors."""
+        rp = _dev(row_ptr, torch.int64)
+        cl = _dev(col, torch.int32)
+        ww = _dev(w, torch.int32)
+        n, total = self.info()
+        g = CGraph(rp.numel() - 1, cl.numel(), rp.data_ptr(), cl.data_ptr() if cl.numel() else None,
+                   ww.data_ptr() if ww.numel() else None)
+        par = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        slot = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        _check(self.lib.chl_labels_parents(self._h, C.byref(g), par.data_ptr(), slot.data_ptr(),
+                                           _stream_ptr(stream)), "chl_labels_parents")
+        return par[:total], slot[:total]
+
+    def path_hops(self, pairs, parent, slot, stream=None):
+        """(hops int64[q], path_off int64[q+1]) device tensors for pairs [q, 2]."""
+        p = _dev(pairs, torch.int32).reshape(-1, 2)
+        q = p.shape[0]
+        hops = torch.empty(max(q, 1), dtype=torch.int64, device="cuda")
+        off = torch.empty(q + 1, dtype=torch.int64, device="cuda")
+        _check(self.lib.chl_query_path_hops(self._h, parent.data_ptr(), slot.data_ptr(), p.data_ptr(), q,
+                                            hops.data_ptr(), off.data_ptr(), _stream_ptr(stream)),
+               "chl_query_path_hops")
+        return hops[:q], off
+
+    def paths(self, pairs, parent, slot, stream=None):
+        """Shortest paths for pairs [q, 2]: (hops int64[q], path_off
+        int64[q+1], path int32[path_off[q]]) device tensors; pair k's vertices
+        are path[path_off[k]:path_off[k+1]], u first and v last."""
+        p = _dev(pairs, torch.int32).reshape(-1, 2)
+        q = p.shape[0]
+        hops, off = self.path_hops(p, parent, slot, stream)
+        total = int(off[q].item())
+        path = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+        _check(self.lib.chl_query_paths(self._h, parent.data_ptr(), slot.data_ptr(), p.data_ptr(), q,
+                                        off.data_ptr(), path.data_ptr(), _stream_ptr(stream)), "chl_query_paths")
+        return hops, off, path[:total]
 
     def stats(self, per_root=False):
         s = CStats()
