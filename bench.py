@@ -152,6 +152,52 @@ def serve_full(chl, gg, stream):
     return out
 
 
+def paths_measure(chl, L, c, d, pairs, stream, reps=3):
+    """Shortest-path extension on a resident labeling: the parents kernel
+    (one launch; HIP events on the build stream, median of reps) against
+    its algorithmic bytes, and path queries (hop counts + path vertices) for
+    the given device pairs. Algorithmic bytes of the parents kernel: 4 per
+    lookup of a label's hub in a neighbour's list (sum over v of
+    deg(v) * |L_v| lookups), 16 per label (its hub and distance read, its
+    parent and slot written), 8 per arc and 32 per vertex (row and label
+    offsets)."""
+    import numpy as np
+    import torch
+    row, col, w = d[0], d[1], d[2]
+    off = L.offsets()
+    deg = np.diff(c["row_ptr"])
+    lab = np.diff(off)
+    lookups = int((deg * lab).sum())
+    total = int(off[-1])
+    alg = 4 * lookups + 16 * total + 8 * int(len(c["col"])) + 32 * int(c["n"])
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        par, slot = L.parents(row, col, w, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    pm = float(np.median(ms))
+    L.paths(pairs[:1000], par, slot, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hops, poff, path = L.paths(pairs, par, slot, stream=stream)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t1
+    h = hops.cpu().numpy()
+    conn = h >= 0
+    achieved = alg / (pm / 1e3) / 1e9
+    r = {"parents_ms": round(pm, 3), "parents_alg_bytes": alg, "lookups": lookups,
+         "parents_roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(achieved / HBM_PEAK_GBS, 5)},
+         "path_pairs": int(len(h)), "path_s": round(ts, 5), "paths_per_s": round(len(h) / ts, 1),
+         "connected": int(conn.sum()), "mean_hops": round(float(h[conn].mean()), 2) if conn.any() else None,
+         "max_hops": int(h.max()), "path_vertices": int(poff[-1].item())}
+    del par, slot, hops, poff, path
+    return r
+
+
 def large_workloads(chl, gg, stream):
     """The other workloads: the 64x64 grid (10^4 queries), the 1024x1024 grid
     with 5% diagonal shortcuts and R-MAT scale 20 (10^6 queries each). Full
@@ -190,6 +236,8 @@ def large_workloads(chl, gg, stream):
         qo = L.query(pairs, out=qo, stream=stream)
         torch.cuda.synchronize()
         qs = len(c["pairs"]) / (time.perf_counter() - t1)
+        npath = 10_000 if nm.startswith("grid") else len(c["pairs"])
+        pth = paths_measure(chl, L, c, d, pairs[:npath], stream)
         L.free()
         r = {"n": c["n"], "edges": c["m"], "build_s": round(min(times), 4), "build_s_runs": [round(t, 4) for t in times],
              "labels": st["labels"], "als": round(st["labels"] / c["n"], 2), "max_label_size": int(sizes.max()),
@@ -202,7 +250,7 @@ def large_workloads(chl, gg, stream):
              "delta": st["delta"], "key_bits": st["key_bits"],
              "phases_ms": {"prep": round(st["prep_ms"], 1), "prefix": round(st["prefix_ms"], 1),
                            "main": round(st["tree_ms"], 1), "assemble": round(st["assemble_ms"], 1)},
-             "queries_per_s": round(qs, 1)}
+             "queries_per_s": round(qs, 1), "paths": pth}
         wc = json.load(open(COUNTS)).get(nm, {})
         if "arcs" in wc:
             r["gteps"] = round(wc["arcs"] / min(times) / 1e9, 4)
@@ -352,6 +400,12 @@ def main():
                 "alg_bytes_per_launch": alg_bytes,
                 "units_per_build": units}
 
+    # shortest-path extension on the resident labeling (outside the timed
+    # steps: an extra build)
+    L = chl.build(row, col, w, order, stream=stream)
+    paths = paths_measure(chl, L, c, (row, col, w), pairs, stream)
+    L.free()
+
     # the same batched build without the common label table (PLaNT trees
     # alone, Section 4.2), for reference
     torch.cuda.synchronize()
@@ -438,6 +492,7 @@ def main():
         "phases_ms": {"prep": round(stats["prep_ms"], 3), "prefix": round(stats["prefix_ms"], 3),
                       "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
         "roofline": roofline, "cpu_baseline": cpu,
+        "paths": paths,
     }
     if serving_full is not None:
         out["serving_full"] = serving_full

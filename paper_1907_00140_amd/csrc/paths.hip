@@ -11,15 +11,23 @@
 // L_p are looked up in L_v. slot = the position of p's label of the same hub
 // within L_p, so that a walk takes one step per edge.
 //
-// k_parents: one wave per vertex v. L_v (up to PCH labels per pass) sits in
-// LDS as sorted hubs, distances and a 64-bit candidate (p << 32 | slot) per
-// label. The arcs of v are taken 64 at a time; each lane owns one arc and
+// k_parents: one wave per vertex v, vertices taken from a queue in rank
+// order (an atomic counter over hub_vertex[]: under a degree ranking the
+// heaviest rows go first, and no wave is left with a run of them, as a fixed
+// stride over input ids would leave one on an R-MAT graph, whose
+// high-degree ids are those with few bits set). A pass whose labels are all
+// v's own (distance 0, no parent) skips the arcs. L_v (up to PCH labels per
+// pass) sits in LDS as sorted hubs, distances and a 64-bit candidate
+// (p << 32 | slot) per label. The arcs of v are taken 64 at a time; each lane owns one arc and
 // the wave splits the flattened (arc, entry of L_p) index space evenly over
 // its lanes (inclusive scan of the list lengths, a 6-step search for the
 // arc of an index), so a hub vertex with thousands of neighbours is spread
 // over the lanes as well as a grid vertex with four. A neighbour list is cut
-// to the hub range of the labels in LDS by two binary searches when it is
-// much longer than that range's labels, or when L_v takes several passes.
+// to the hub range of the labels in LDS by binary search: above, when its
+// last hub lies beyond the range (every hub of L_v ranks at most as low as
+// v itself, so for the important, high-degree vertices of a degree ranking
+// this drops nearly all of each neighbour's list), and below when L_v takes
+// several passes.
 // A matching entry (same hub, d(p,h) + w = d) takes an LDS atomic minimum.
 //
 // k_path: a group of G lanes per pair finds the hub by the merge of the two
@@ -38,7 +46,7 @@ namespace chl {
 namespace {
 
 constexpr int PW = 4;       // waves per workgroup of k_parents
-constexpr int PCH = 512;    // labels of L_v per LDS pass
+constexpr int PCH = 256;    // labels of L_v per LDS pass
 
 struct ParentLds {
     unsigned long long cand[PCH];
@@ -72,12 +80,21 @@ __global__ __launch_bounds__(64 * PW) void k_parents(int32_t n, int64_t m, const
                                                      const int32_t* __restrict__ col, const int32_t* __restrict__ wt,
                                                      const int64_t* __restrict__ off, const int32_t* __restrict__ hub,
                                                      const int32_t* __restrict__ dist, int32_t* __restrict__ parent,
-                                                     int32_t* __restrict__ slot, int32_t* err) {
+                                                     int32_t* __restrict__ slot, const int32_t* __restrict__ vorder,
+                                                     unsigned long long* next, int32_t* err) {
     __shared__ ParentLds lds[PW];
     const int lane = threadIdx.x & 63;
     ParentLds& S = lds[threadIdx.x >> 6];
-    const int64_t nw = (int64_t)gridDim.x * PW;
-    for (int64_t v = (int64_t)blockIdx.x * PW + (threadIdx.x >> 6); v < n; v += nw) {
+    for (;;) {
+        unsigned long long idx = 0;
+        if (lane == 0) idx = atomicAdd(next, 1ull);
+        idx = __shfl(idx, 0);
+        if (idx >= (unsigned long long)n) break;
+        const int32_t v = vorder[idx];
+        if (v < 0 || v >= n) {
+            if (lane == 0) atomicOr(err, ERR_BIT_INVALID);
+            continue;
+        }
         const int64_t lb = off[v], le = off[v + 1];
         int64_t eb = row[v], ee = row[v + 1];
         if (eb < 0 || ee < eb || ee > m) {          // malformed row: no arcs, flagged
@@ -93,8 +110,11 @@ __global__ __launch_bounds__(64 * PW) void k_parents(int32_t n, int64_t m, const
             }
             const bool whole = c0 == lb && c0 + cn == le;
             const int32_t hlo = hub[c0], hhi = hub[c0 + cn - 1];
+            bool far = false;                          // some label of the pass is not v's own
+            for (int i = lane; i < cn; i += 64) far |= dist[c0 + i] != 0;
+            const bool any_far = __ballot(far) != 0;
             wave_sync();
-            for (int64_t e0 = eb; e0 < ee; e0 += 64) {
+            for (int64_t e0 = any_far ? eb : ee; e0 < ee; e0 += 64) {
                 const int64_t e = e0 + lane;
                 int64_t len = 0, beg = 0, base = 0;
                 int32_t p = 0, w = 0;
@@ -104,11 +124,8 @@ __global__ __launch_bounds__(64 * PW) void k_parents(int32_t n, int64_t m, const
                     if (p >= 0 && p < n && w >= 1) {
                         base = off[p];
                         int64_t end = off[p + 1];
-                        beg = base;
-                        if (!whole || end - base > 4 * (int64_t)cn) {
-                            beg = lower_hub(hub, base, end, hlo);
-                            end = lower_hub(hub, beg, end, hhi + 1);
-                        }
+                        beg = !whole ? lower_hub(hub, base, end, hlo) : base;
+                        if (end > beg && hub[end - 1] > hhi) end = lower_hub(hub, beg, end, hhi + 1);
                         len = end - beg;
                     } else {
                         atomicOr(err, ERR_BIT_INVALID);
@@ -317,12 +334,19 @@ extern "C" int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32
     if (h->total > 0 && (!parent || !slot)) return CHL_ERR_INVALID_ARG;
     if (h->total == 0 || h->n == 0) return CHL_OK;
     hipStream_t st = (hipStream_t)stream;
-    return with_err(h, st, [&]() {
-        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)h->n + PW - 1) / PW, 4096));
+    // the vertex queue's counter
+    auto* next = (unsigned long long*)h->alloc.alloc(256, h->alloc.ctx);
+    if (!next) return CHL_ERR_OOM;
+    const int rc = with_err(h, st, [&]() {
+        if (hipMemsetAsync(next, 0, 8, st) != hipSuccess) return CHL_ERR_HIP;
+        const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(((int64_t)h->n + PW - 1) / PW, 2048));
         hipLaunchKernelGGL(k_parents, dim3(blocks), dim3(64 * PW), 0, st, h->n, g->n_arcs, g->row_ptr, g->col,
-                           g->w, h->offsets, h->hub_pos, h->dist, parent, slot, h->qerr);
+                           g->w, h->offsets, h->hub_pos, h->dist, parent, slot, h->order, next, h->qerr);
         return hipGetLastError() == hipSuccess ? CHL_OK : CHL_ERR_HIP;
     });
+    (void)hipStreamSynchronize(st);
+    h->alloc.free(next, h->alloc.ctx);
+    return rc;
 }
 
 extern "C" int chl_query_path_hops(const chl_labels* h, const int32_t* parent, const int32_t* slot,
