@@ -122,6 +122,50 @@ def rmat_edges(scale, edge_factor, a, b, c, seed, wlo, whi):
     return n, u, v, _weights(len(u), wlo, whi, seed + 7919)
 
 
+def rmat_arcs(scale, edge_factor, a, b, c, seed, wlo, whi):
+    """Directed R-MAT graph: the samples of ``rmat_edges`` read as arcs u -> v
+    (row quadrant = source), self-loops and duplicate arcs removed, sorted by
+    (u, v). Weights, one per arc in that order: PCG64(seed + 7919)."""
+    n = 1 << scale
+    s = edge_factor * n
+    g = _rng(seed)
+    u = np.zeros(s, dtype=np.int64)
+    v = np.zeros(s, dtype=np.int64)
+    ab, abc = a + b, a + b + c
+    for lvl in range(scale):
+        x = g.random(s)
+        bit = np.int64(1 << (scale - 1 - lvl))
+        right = ((x >= a) & (x < ab)) | (x >= abc)
+        down = x >= ab
+        v += np.where(right, bit, 0)
+        u += np.where(down, bit, 0)
+    keep = u != v
+    key = np.unique(u[keep] * np.int64(n) + v[keep])
+    u, v = key // n, key % n
+    return n, u, v, _weights(len(u), wlo, whi, seed + 7919)
+
+
+def to_csr_directed(n, u, v, w):
+    """Out-arc CSR of a directed arc list (row u holds u -> v), rows sorted by col."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    w = np.asarray(w, dtype=np.int32)
+    perm = np.lexsort((v, u))
+    u, v, w = u[perm], v[perm], w[perm]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(u, minlength=n), out=row_ptr[1:])
+    return row_ptr, v.astype(np.int32), w.astype(np.int32)
+
+
+def transpose_csr(row_ptr, col, w):
+    """CSR of the reversed graph (row v holds the arcs u -> v as v <- u),
+    rows sorted by col."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    return to_csr_directed(n, np.asarray(col, dtype=np.int64), src, w)
+
+
 def random_edges(n, m, wlo, whi, seed):
     """Uniform random graph: m endpoint pairs from PCG64(seed), then
     canonicalised (so fewer than m edges may remain). Weights from
@@ -160,6 +204,16 @@ def degree_rank(row_ptr, seed):
     return order.astype(np.int32)
 
 
+def degree_rank_directed(row_ptr, col, seed):
+    """Ranking of a directed graph by total degree (out + in) descending;
+    ties as in ``degree_rank``."""
+    n = len(row_ptr) - 1
+    deg = np.diff(np.asarray(row_ptr, dtype=np.int64)) + np.bincount(np.asarray(col, dtype=np.int64), minlength=n)
+    ids = np.arange(n, dtype=np.uint64)
+    h = mix64(ids ^ np.uint64(seed))
+    return np.lexsort((ids, h, -deg)).astype(np.int32)
+
+
 def random_rank(n, seed):
     """Uniformly random ranking: a PCG64(seed) permutation."""
     return _rng(seed).permutation(n).astype(np.int32)
@@ -185,10 +239,25 @@ def make_config(name):
                   seed 3, degree rank (tie seed 3).
     rmat20      : R-MAT scale 20, 8n samples, seed 4, weights [1,65536],
                   degree rank (tie seed 4).
+    rmat16dir   : directed R-MAT scale 16 (the samples read as arcs), seed 5,
+                  weights [1,1000], total-degree rank (tie seed 5), 10^6 pairs
+                  seed 105; out-arc CSR, "directed": True.
     rmat<s>_<i> : serving build requests, R-MAT scale s, seed 500+i,
                   weights [1,1000], degree rank.
-    Smaller stand-ins used by tests: grid<r>x<c>_<seed>, rmat<s>s<seed>.
+    Smaller stand-ins used by tests: grid<r>x<c>_<seed>, rmat<s>s<seed>,
+    rmat<s>d<seed> (directed).
     """
+    if name == "rmat16dir" or (name.startswith("rmat") and name[4:].replace("d", "", 1).isdigit() and "d" in name[4:]):
+        if name == "rmat16dir":
+            sc, sd, qseed, q = 16, 5, 105, 1_000_000
+        else:
+            sc, sd = (int(t) for t in name[4:].split("d"))
+            qseed, q = sd + 100, 10_000
+        n, u, v, w = rmat_arcs(sc, 8, *RMAT_ABC, sd, 1, 1000)
+        row_ptr, col, ww = to_csr_directed(n, u, v, w)
+        order = degree_rank_directed(row_ptr, col, sd)
+        return {"name": name, "n": n, "m": len(u), "row_ptr": row_ptr, "col": col, "w": ww, "order": order,
+                "pairs": query_pairs(n, q, qseed), "directed": True}
     if name == "grid64":
         n, u, v, w = grid_edges(64, 64, 1, 100, 1)
         seed, qseed, q = 1, 101, 10_000

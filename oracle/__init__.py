@@ -64,6 +64,7 @@ def load(path=None):
     lib.oracle_run_free.argtypes = [vp]
     lib.oracle_query.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
     lib.oracle_sssp.argtypes = [C.c_int32, vp, vp, vp, C.c_int32, vp]
+    lib.oracle_query2.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int64, vp]
     lib.oracle_parents.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.oracle_paths.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int64, vp, vp, vp]
     if path is None:
@@ -246,3 +247,40 @@ def paths(labels, parent, slot, pairs, lib=None):
     lib.oracle_paths(off.ctypes.data, hub.ctypes.data, dist.ctypes.data, par.ctypes.data, sl.ctypes.data,
                      pairs.ctypes.data, q, hops.ctypes.data, path_off.ctypes.data, path.ctypes.data)
     return hops, path_off, path[:int(path_off[-1])]
+
+
+def _transpose(row_ptr, col, w):
+    """CSR of the reversed graph: row v lists the arcs u -> v as (u, w)."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    dst = np.asarray(col, dtype=np.int64)
+    p = np.lexsort((src, dst))
+    trow = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(dst, minlength=n), out=trow[1:])
+    return trow, src[p].astype(np.int32), np.asarray(w, dtype=np.int32)[p]
+
+
+def chl_directed(row_ptr, col, w, order, mode=MODE_PLANT, threads=None, lib=None):
+    """CHL of a directed graph given by its out-arc CSR (footnote of Section
+    1): (L_out, L_in). L_in(v) holds (h, d(h, v)) from the trees grown along
+    the arcs; L_out(v) holds (h, d(v, h)) from the trees grown on the
+    reversed graph. Only the PLaNT modes apply (the definition form needs a
+    symmetric graph)."""
+    assert mode in (MODE_PLANT, MODE_PLANT_FULL)
+    lab_in = chl(row_ptr, col, w, order, mode=mode, threads=threads, lib=lib)
+    trow, tcol, tw = _transpose(row_ptr, col, w)
+    lab_out = chl(trow, tcol, tw, order, mode=mode, threads=threads, lib=lib)
+    return lab_out, lab_in
+
+
+def query_directed(lab_out, lab_in, pairs, lib=None):
+    """d(u, v) for int32 pairs [q, 2] from L_out(u) and L_in(v); -1 if none."""
+    lib = lib or load()
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    out = np.zeros(len(pairs), dtype=np.int64)
+    a = [np.ascontiguousarray(x, dtype=t) for x, t in ((lab_out.offsets, np.int64), (lab_out.hub_pos, np.int32),
+                                                      (lab_out.dist, np.int64), (lab_in.offsets, np.int64),
+                                                      (lab_in.hub_pos, np.int32), (lab_in.dist, np.int64))]
+    lib.oracle_query2(*(x.ctypes.data for x in a), pairs.ctypes.data, len(pairs), out.ctypes.data)
+    return out

@@ -43,9 +43,14 @@
  * hub first (Algorithm 2's sort step; the query merge of Section 5 relies on
  * it). oracle_query() answers distance queries by the sorted-list merge of
  * Section 5 (QLSN): the minimum of d_u + d_v over common hubs, -1 when the
- * lists share no hub. oracle_parents() and oracle_paths() add the
- * shortest-path extension of Section 4.4: per label the next vertex towards
- * its hub, and paths as two chains of parents joined at the common hub.
+ * lists share no hub. The definition form scans a vertex's own row for its
+ * shortest-path predecessors, so it needs a symmetric graph; for a directed
+ * graph the PLaNT form run on the graph gives the in-labels (trees grown
+ * along the arcs) and run on the reversed graph the out-labels, and
+ * oracle_query2() merges L_out(u) with L_in(v). oracle_parents() and
+ * oracle_paths() add the shortest-path extension of Section 4.4: per label
+ * the next vertex towards its hub, and paths as two chains of parents joined
+ * at the common hub.
  */
 #include <pthread.h>
 #include <stdatomic.h>
@@ -544,6 +549,29 @@ void oracle_query(const int64_t* offsets, const int32_t* hub_pos, const int64_t*
                   const int32_t* pairs, int64_t q, int64_t* out) {
     for (int64_t k = 0; k < q; k++)
         out[k] = merge_query(offsets, hub_pos, dist, pairs[2 * k], pairs[2 * k + 1]);
+}
+
+/* Directed graphs (footnote of Section 1): two label sets, L_out(u) with
+ * hubs reached from u and L_in(v) with hubs that reach v; d(u, v) is the
+ * minimum of d(u, h) + d(h, v) over hubs common to L_out(u) and L_in(v). */
+void oracle_query2(const int64_t* off_out, const int32_t* hub_out, const int64_t* dist_out,
+                   const int64_t* off_in, const int32_t* hub_in, const int64_t* dist_in,
+                   const int32_t* pairs, int64_t q, int64_t* out) {
+    for (int64_t k = 0; k < q; k++) {
+        int32_t u = pairs[2 * k], v = pairs[2 * k + 1];
+        int64_t i = off_out[u], ie = off_out[u + 1], j = off_in[v], je = off_in[v + 1];
+        int64_t best = -1;
+        while (i < ie && j < je) {
+            if (hub_out[i] < hub_in[j]) i++;
+            else if (hub_out[i] > hub_in[j]) j++;
+            else {
+                int64_t s = dist_out[i] + dist_in[j];
+                if (best < 0 || s < best) best = s;
+                i++; j++;
+            }
+        }
+        out[k] = best;
+    }
 }
 
 /* Plain Dijkstra distances from src; -1 for unreachable vertices. */

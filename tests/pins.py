@@ -488,6 +488,84 @@ def check_path_graph_walks(lib, n, seed):
         assert hops[k] == abs(u - v)
 
 
+# ---------------------------------------------------------------- directed graphs
+def csr_from_arcs(n, arcs):
+    """Out-arc CSR of directed arcs (u, v, w); may hold parallel arcs and loops."""
+    a = np.asarray(list(arcs), dtype=np.int64).reshape(-1, 3)
+    p = np.lexsort((a[:, 1], a[:, 0]))
+    a = a[p]
+    row = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(a[:, 0], minlength=n), out=row[1:])
+    return row, a[:, 1].astype(np.int32), a[:, 2].astype(np.int32)
+
+
+def check_directed_bruteforce(lib, n, m, wmax, seed):
+    """Random directed multigraph: L_out(v) holds (h, d(v,h)) exactly when h
+    tops every shortest v->h path, L_in(v) holds (h, d(h,v)) exactly when h
+    tops every shortest h->v path (the definition on Floyd-Warshall
+    distances of the arcs, and of the reversed arcs), and the merge of
+    L_out(u) with L_in(v) gives d(u, v) for all pairs."""
+    g = np.random.default_rng(seed)
+    a = [(int(x), int(y), int(z)) for x, y, z in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = csr_from_arcs(n, a)
+    order = gg.random_rank(n, seed)
+    D = floyd_warshall(n, row, col, w)
+    want_out, want_in = brute_labels(D, order), brute_labels(np.ascontiguousarray(D.T), order)
+    for mode in (oracle.MODE_PLANT, oracle.MODE_PLANT_FULL):
+        lo, li = oracle.chl_directed(row, col, w, order, mode=mode, threads=2, lib=lib)
+        assert oracle_labels(lo) == want_out and oracle_labels(li) == want_in, mode
+    uu, vv = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    pairs = np.stack([uu.ravel(), vv.ravel()], 1).astype(np.int32)
+    q = oracle.query_directed(lo, li, pairs, lib=lib).reshape(n, n)
+    assert np.array_equal(q, np.where(D >= INF, -1, D))
+
+
+def check_directed_cycle(lib, n, seed):
+    """Directed cycle 0 -> 1 -> ... -> n-1 -> 0: the only v->h path runs
+    forward around the cycle, so (h, .) is in L_out(v) iff h has the
+    smallest rank position on the arc v..h, and in L_in(v) iff on h..v."""
+    g = np.random.default_rng(seed)
+    ws = g.integers(1, 9, n)
+    row, col, w = csr_from_arcs(n, [(i, (i + 1) % n, int(ws[i])) for i in range(n)])
+    order = gg.random_rank(n, seed)
+    pos = pos_of(order)
+
+    def seg(a, b):                    # vertices a, a+1, ..., b (mod n) and the length a -> b
+        k = (b - a) % n
+        vs = [(a + t) % n for t in range(k + 1)]
+        return vs, int(sum(ws[(a + t) % n] for t in range(k)))
+
+    want_out = {v: [] for v in range(n)}
+    want_in = {v: [] for v in range(n)}
+    for v in range(n):
+        for h in range(n):
+            vs, d = seg(v, h)
+            if min(pos[x] for x in vs) == pos[h]:
+                want_out[v].append((int(pos[h]), d))
+            vs, d = seg(h, v)
+            if min(pos[x] for x in vs) == pos[h]:
+                want_in[v].append((int(pos[h]), d))
+    for v in range(n):
+        want_out[v].sort()
+        want_in[v].sort()
+    lo, li = oracle.chl_directed(row, col, w, order, threads=2, lib=lib)
+    assert oracle_labels(lo) == want_out and oracle_labels(li) == want_in
+
+
+def check_symmetric_as_directed(lib, n, m, seed):
+    """An undirected graph given as its two arcs per edge: both label sets
+    equal the undirected labeling."""
+    g = np.random.default_rng(seed)
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, 4, m))]
+    row, col, w = csr_from_edges(n, e)
+    order = gg.random_rank(n, seed)
+    lab = oracle.chl(row, col, w, order, mode=oracle.MODE_DEFINITION, threads=2, lib=lib)
+    lo, li = oracle.chl_directed(row, col, w, order, threads=2, lib=lib)
+    assert oracle_labels(lo) == oracle_labels(lab) == oracle_labels(li)
+
+
 def run_all(lib):
     """Every pin, smallish; used against planted mistakes."""
     check_golden(lib, "fig1_example.txt")
@@ -509,3 +587,7 @@ def run_all(lib):
     for s in range(4):
         check_paths_bruteforce(lib, 22, 40, 2 + s % 2, 400 + s)
     check_path_graph_walks(lib, 14, 8)
+    for s in range(4):
+        check_directed_bruteforce(lib, 20, 50, 1 + s % 3, 600 + s)
+    check_directed_cycle(lib, 9, 3)
+    check_symmetric_as_directed(lib, 25, 40, 7)

@@ -217,3 +217,27 @@ def test_parents_grid64_against_dijkstra(lib):
         P = path[poff[k]:poff[k + 1]].tolist()
         assert P[0] == u and P[-1] == v and len(P) == hops[k] + 1
         assert sum(wt[(P[t], P[t + 1])] for t in range(len(P) - 1)) == d[k]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_directed_bruteforce(lib, seed):
+    pins.check_directed_bruteforce(lib, 15 + 4 * seed, 30 + 12 * seed, 1 + seed % 4, 700 + seed)
+
+
+def test_directed_closed_forms(lib):
+    for s in range(3):
+        pins.check_directed_cycle(lib, 7 + 3 * s, s)
+        pins.check_symmetric_as_directed(lib, 30 + s, 60, s)
+
+
+def test_directed_rmat10_queries_match_dijkstra(lib):
+    """Directed R-MAT 10: queries from the two label sets equal Dijkstra over
+    the arcs from sampled sources."""
+    c = gg.make_config("rmat10d3")
+    lo, li = oracle.chl_directed(c["row_ptr"], c["col"], c["w"], c["order"], lib=lib)
+    pairs = c["pairs"][:3000]
+    q = oracle.query_directed(lo, li, pairs, lib=lib)
+    for s in np.unique(pairs[:40, 0]):
+        ref = oracle.sssp(c["row_ptr"], c["col"], c["w"], int(s), lib=lib)
+        sel = pairs[:, 0] == s
+        assert np.array_equal(q[sel], ref[pairs[sel, 1]])

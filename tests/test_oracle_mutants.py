@@ -51,6 +51,11 @@ MUTANTS = {
                  "if (best < 0 || s <= best) { best = s; bi = i; bj = j; }"),
     # path: v's half not reversed
     "path_reverse": ("o[hu + 1 + t] = tmp[hv - 1 - t];", "o[hu + 1 + t] = tmp[t];"),
+    # directed query keeps the largest common-hub sum
+    "query2_max": ("int64_t s = dist_out[i] + dist_in[j];\n                if (best < 0 || s < best) best = s;",
+                   "int64_t s = dist_out[i] + dist_in[j];\n                if (best < 0 || s > best) best = s;"),
+    # directed query merge advances the wrong list
+    "query2_skip": ("if (hub_out[i] < hub_in[j]) i++;", "if (hub_out[i] < hub_in[j]) j++;"),
     "sssp_w": ("int64_t nd = it.d + wt[e];\n            if (nd < out[col[e]])",
                "int64_t nd = it.d + wt[row_ptr[it.v]];\n            if (nd < out[col[e]])"),
 }
