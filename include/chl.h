@@ -17,7 +17,8 @@
  *
  * Conventions shared by every call:
  *   - The graph is undirected with positive int32 edge weights, given as a
- *     symmetric CSR; ids are 0..n-1 ("input ids").
+ *     symmetric CSR; ids are 0..n-1 ("input ids"). chl_build_directed takes
+ *     the out-arc CSR of a directed graph instead.
  *   - The ranking is a permutation order[0..n-1]; order[0] is the most
  *     important vertex. The rank position of v is pos(v), with order[pos(v)]
  *     = v. Hubs are reported by rank position ("hub_pos"), so L_v is sorted
@@ -157,6 +158,37 @@ typedef struct chl_labels chl_labels;
 int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
               const chl_allocator* alloc, void* stream, chl_labels** out);
 
+/* ---- directed graphs (footnote of Section 1: every vertex gets forward and
+ * backward labels, and a query merges the source's with the target's) ----
+ * g holds the out-arcs of a directed graph (row v lists the arcs v -> col[e];
+ * no symmetry is required; the other conditions of chl_graph apply). The
+ * handle holds two labelings under the same ranking: L_out(v) = the labels
+ * (h, d(v, h)) such that h is the highest ranked vertex on every shortest
+ * v -> h path (trees grown on the reversed graph), and L_in(v) = the labels
+ * (h, d(h, v)) such that h tops every shortest h -> v path (trees grown along
+ * the arcs). chl_query answers d(u, v) = min over hubs common to L_out(u) and
+ * L_in(v) of d(u, h) + d(h, v); chl_labels_info and chl_labels_export give
+ * L_out, chl_labels_export_in gives L_in. The options apply to both builds
+ * except prune_hubs, which is ignored (rank-prefix pruning is off: its test
+ * would need both label sets of the prefix). Per-root statistics are not
+ * kept (chl_build_stats with per_root != NULL returns CHL_ERR_INVALID_ARG);
+ * the totals add up both builds. chl_labels_parents and the path queries
+ * return CHL_ERR_INVALID_ARG on a directed handle. Synchronises `stream`.
+ * Errors as for chl_build. */
+int chl_build_directed(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
+                       const chl_allocator* alloc, void* stream, chl_labels** out);
+
+/* 1 for a directed labeling (then *in_total = number of in-labels), 0 for an
+ * undirected one (*in_total = total), CHL_ERR_INVALID_ARG for NULL. in_total
+ * may be NULL. */
+int chl_labels_directed(const chl_labels* h, int64_t* in_total);
+
+/* Copy the in-labels of a directed labeling out, in the layout of
+ * chl_labels_export (offsets[n+1], hub_pos[in_total], dist[in_total]).
+ * CHL_ERR_INVALID_ARG for an undirected handle. */
+int chl_labels_export_in(const chl_labels* h, int64_t* offsets, int32_t* hub_pos,
+                         int32_t* dist, int to_host, void* stream);
+
 /* Number of vertices and total number of labels (host outputs). */
 int chl_labels_info(const chl_labels* h, int32_t* n, int64_t* total);
 
@@ -175,7 +207,8 @@ int chl_labels_hub_vertex(const chl_labels* h, int32_t* hub_vertex, int to_host,
 /* Point-to-point shortest distance queries by sorted-list merge of the two
  * label sets (Section 5, single-copy mode): pairs[2q] = (u0, v0, u1, v1, ...)
  * int32 input ids on the device; out[q] int64 on the device receives
- * d(u,v), 0 when u == v, -1 when u and v are in different components.
+ * d(u,v), 0 when u == v, -1 when u and v are in different components (for a
+ * directed labeling: when no path leads from u to v).
  * q = 0 is a no-op. Synchronises `stream` (ids are validated on the device);
  * an id outside [0, n) gives CHL_ERR_INVALID_ARG (out is then unspecified). */
 int chl_query(const chl_labels* h, const int32_t* pairs, int64_t q, int64_t* out, void* stream);

@@ -85,6 +85,9 @@ def load(path=LIB_PATH):
             "chl_build_opts_default": (None, [vp]),
             "chl_build": (C.c_int, [vp, vp, vp, vp, vp, vp]),
             "chl_labels_info": (C.c_int, [vp, vp, vp]),
+            "chl_build_directed": (C.c_int, [vp, vp, vp, vp, vp, vp]),
+            "chl_labels_directed": (C.c_int, [vp, vp]),
+            "chl_labels_export_in": (C.c_int, [vp, vp, vp, vp, C.c_int, vp]),
             "chl_labels_export": (C.c_int, [vp, vp, vp, vp, C.c_int, vp]),
             "chl_labels_hub_vertex": (C.c_int, [vp, vp, C.c_int, vp]),
             "chl_query": (C.c_int, [vp, vp, i64, vp, vp]),
@@ -211,6 +214,30 @@ class Labels:
                                           _stream_ptr(stream)), "chl_labels_export")
         return off, hub[:total], dist[:total]
 
+    @property
+    def directed(self):
+        return self.lib.chl_labels_directed(self._h, None) == 1
+
+    def export_in(self, device="cpu", stream=None):
+        """In-labels of a directed labeling, laid out as export()."""
+        n, _ = self.info()
+        tot = C.c_int64()
+        self.lib.chl_labels_directed(self._h, C.byref(tot))
+        total = tot.value
+        if str(device) == "cpu":
+            off = np.zeros(n + 1, np.int64)
+            hub = np.zeros(max(total, 1), np.int32)
+            dist = np.zeros(max(total, 1), np.int32)
+            _check(self.lib.chl_labels_export_in(self._h, off.ctypes.data, hub.ctypes.data, dist.ctypes.data, 1,
+                                                 _stream_ptr(stream)), "chl_labels_export_in")
+            return torch.from_numpy(off), torch.from_numpy(hub[:total]), torch.from_numpy(dist[:total])
+        off = torch.empty(n + 1, dtype=torch.int64, device=device)
+        hub = torch.empty(max(total, 1), dtype=torch.int32, device=device)
+        dist = torch.empty(max(total, 1), dtype=torch.int32, device=device)
+        _check(self.lib.chl_labels_export_in(self._h, off.data_ptr(), hub.data_ptr(), dist.data_ptr(), 0,
+                                             _stream_ptr(stream)), "chl_labels_export_in")
+        return off, hub[:total], dist[:total]
+
     def offsets(self, stream=None):
         """offsets int64[n+1] (by input id) on the host, without the label arrays."""
         n, _ = self.info()
@@ -304,10 +331,11 @@ class Labels:
 
 def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, delta=0,
           early_term=True, stats=True, autotune=True, roots=None, prune_hubs=0, team_wgs=0,
-          stream=None, allocator="torch"):
+          stream=None, allocator="torch", directed=False):
     """chl_build over a symmetric CSR (row_ptr int64, col int32, w int32) and a
     ranking order (order[0] most important). roots = (begin, count, stride)
-    restricts the build to those root rank positions. Returns Labels."""
+    restricts the build to those root rank positions. directed=True: the CSR
+    holds the out-arcs of a directed graph (chl_build_directed). Returns Labels."""
     lib = load()
     rp = _dev(row_ptr, torch.int64)
     cl = _dev(col, torch.int32)
@@ -331,7 +359,8 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
     o.team_wgs = int(team_wgs)
     al = default_allocator() if allocator == "torch" else None
     out = C.c_void_p()
-    code = lib.chl_build(C.byref(g), od.data_ptr(), C.byref(o), C.byref(al.c) if al else None,
-                         _stream_ptr(stream), C.byref(out))
-    _check(code, "chl_build")
+    f = lib.chl_build_directed if directed else lib.chl_build
+    code = f(C.byref(g), od.data_ptr(), C.byref(o), C.byref(al.c) if al else None, _stream_ptr(stream),
+             C.byref(out))
+    _check(code, "chl_build_directed" if directed else "chl_build")
     return Labels(out.value, al)

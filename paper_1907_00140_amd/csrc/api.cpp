@@ -415,7 +415,9 @@ uint64_t graph_signature(const chl_graph* g, const int32_t* order, int64_t* dev_
 }  // namespace
 
 static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
-                          const chl_allocator* alloc_in, void* stream, chl_labels** out);
+                          const chl_allocator* alloc_in, void* stream, chl_labels** out, bool directed);
+static int chl_build_directed_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
+                                   const chl_allocator* alloc_in, void* stream, chl_labels** out);
 
 // ====================================================================== ABI
 extern "C" {
@@ -445,10 +447,37 @@ void chl_build_opts_default(chl_build_opts* o) {
 int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
               const chl_allocator* alloc, void* stream, chl_labels** out) {
     try {
-        return chl_build_impl(g, order, opts, alloc, stream, out);
+        return chl_build_impl(g, order, opts, alloc, stream, out, false);
     } catch (...) {
         return CHL_ERR_OOM;
     }
+}
+
+int chl_build_directed(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
+                       const chl_allocator* alloc, void* stream, chl_labels** out) {
+    try {
+        return chl_build_directed_impl(g, order, opts, alloc, stream, out);
+    } catch (...) {
+        return CHL_ERR_OOM;
+    }
+}
+
+int chl_labels_directed(const chl_labels* h, int64_t* in_total) {
+    if (!h) return CHL_ERR_INVALID_ARG;
+    if (in_total) *in_total = h->directed ? h->in_total : h->total;
+    return h->directed ? 1 : 0;
+}
+
+int chl_labels_export_in(const chl_labels* h, int64_t* offsets, int32_t* hub_pos, int32_t* dist, int to_host,
+                         void* stream) {
+    if (!h || !h->directed) return CHL_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    hipMemcpyKind k = to_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice;
+    if (offsets) HIPCHK(hipMemcpyAsync(offsets, h->in_offsets, (size_t)(h->n + 1) * 8, k, st));
+    if (hub_pos && h->in_total) HIPCHK(hipMemcpyAsync(hub_pos, h->in_hub_pos, (size_t)h->in_total * 4, k, st));
+    if (dist && h->in_total) HIPCHK(hipMemcpyAsync(dist, h->in_dist, (size_t)h->in_total * 4, k, st));
+    if (to_host) HIPCHK(hipStreamSynchronize(st));
+    return CHL_OK;
 }
 
 int chl_labels_info(const chl_labels* h, int32_t* n, int64_t* total) {
@@ -488,7 +517,9 @@ int chl_query(const chl_labels* hc, const int32_t* pairs, int64_t q, int64_t* ou
     std::lock_guard<std::mutex> lk(h->qmu);
     HIPCHK(hipMemsetAsync(h->qerr, 0, 4, st));
     double avg = h->n ? (double)h->total / h->n : 1.0;
-    if (launch_query(h->n, h->offsets, h->hub_pos, h->dist, pairs, q, out, h->qerr, avg, st))
+    const bool dir = h->directed != 0;
+    if (launch_query(h->n, h->offsets, h->hub_pos, h->dist, dir ? h->in_offsets : h->offsets,
+                     dir ? h->in_hub_pos : h->hub_pos, dir ? h->in_dist : h->dist, pairs, q, out, h->qerr, avg, st))
         return CHL_ERR_HIP;
     int32_t e = 0;
     HIPCHK(hipMemcpyAsync(&e, h->qerr, 4, hipMemcpyDeviceToHost, st));
@@ -518,6 +549,9 @@ void chl_labels_free(chl_labels* h) {
     f(h->order);
     f(h->per_root);
     f(h->qerr);
+    f(h->in_offsets);
+    f(h->in_hub_pos);
+    f(h->in_dist);
     delete h;
 }
 
@@ -702,7 +736,7 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
 }
 
 static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
-                          const chl_allocator* alloc_in, void* stream, chl_labels** out) {
+                          const chl_allocator* alloc_in, void* stream, chl_labels** out, bool directed) {
     if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
     if (g->n < 1 || g->n > 0x7FFFFFFE || g->n_arcs < 0 || g->n_arcs > 0xFFFFFFFFll) return CHL_ERR_INVALID_ARG;
     if (!g->row_ptr || (g->n_arcs > 0 && (!g->col || !g->w))) return CHL_ERR_INVALID_ARG;
@@ -763,7 +797,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (launch_scan_i64(rdeg, rrow, n, scan_tmp, st)) return CHL_ERR_HIP;
     if (launch_renumber(n, B.m, g->row_ptr, g->col, g->w, order, pos, rrow, rarc, st)) return CHL_ERR_HIP;
     if (launch_segsort_u64(rarc, rrow, n, B.m, nullptr, st)) return CHL_ERR_HIP;
-    if (launch_check_symmetric(n, B.m, rrow, rarc, err, st)) return CHL_ERR_HIP;
+    if (!directed && launch_check_symmetric(n, B.m, rrow, rarc, err, st)) return CHL_ERR_HIP;
     HIPCHK(hipMemcpyAsync(hub_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(hc0->c32, err, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -1060,4 +1094,80 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = bv;
     return 0;
+}
+
+// Directed graphs (footnote of Section 1): the trees grown along the arcs
+// give, at every vertex they reach clean, the in-label (h, d(h, v)); the
+// trees grown on the reversed graph give the out-label (h, d(v, h)). Both
+// are ordinary builds (the second on the reversed CSR, made on the device),
+// without the rank-prefix pruning, whose test would need the out-labels of
+// the prefix for the root and the in-labels for the vertex.
+static int chl_build_directed_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
+                                   const chl_allocator* alloc_in, void* stream, chl_labels** out) {
+    if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
+    chl_build_opts o;
+    chl_build_opts_default(&o);
+    if (opts_in) o = *opts_in;
+    if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
+    o.prune_hubs = -1;
+    chl_labels* fwd = nullptr;
+    if (int r = chl_build_impl(g, order, &o, alloc_in, stream, &fwd, true)) return r;   // validates g
+    chl_allocator al = alloc_in ? *alloc_in : kDefaultAlloc;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = g->n;
+    const int64_t m = g->n_arcs;
+    int r = CHL_OK;
+    chl_labels* bwd = nullptr;
+    {
+        Arena A(al);
+        int32_t* cnt = A.get<int32_t>(n);
+        int64_t* trow = A.get<int64_t>((size_t)n + 1);
+        auto* cursor = A.get<unsigned long long>(n);
+        uint64_t* tkey = A.get<uint64_t>((size_t)std::max<int64_t>(m, 1));
+        int32_t* tcol = A.get<int32_t>((size_t)std::max<int64_t>(m, 1));
+        int32_t* tw = A.get<int32_t>((size_t)std::max<int64_t>(m, 1));
+        void* tmp = A.get<uint8_t>(scan_temp_bytes(std::max<int64_t>(n, 1)));
+        if (A.oom) r = CHL_ERR_OOM;
+        else if (launch_transpose(n, m, g->row_ptr, g->col, g->w, cnt, trow, cursor, tkey, tcol, tw, tmp, st))
+            r = CHL_ERR_HIP;
+        if (!r) {
+            chl_graph gt{n, m, trow, tcol, tw};
+            r = chl_build_impl(&gt, order, &o, alloc_in, stream, &bwd, true);
+        }
+        if (hipStreamSynchronize(st) != hipSuccess && !r) r = CHL_ERR_HIP;
+    }
+    if (r) {
+        chl_labels_free(fwd);
+        return r;
+    }
+    bwd->directed = 1;
+    bwd->in_total = fwd->total;
+    bwd->in_offsets = fwd->offsets;
+    bwd->in_hub_pos = fwd->hub_pos;
+    bwd->in_dist = fwd->dist;
+    fwd->offsets = nullptr;
+    fwd->hub_pos = nullptr;
+    fwd->dist = nullptr;
+    chl_stats& S = bwd->st;
+    const chl_stats& F = fwd->st;
+    S.labels += F.labels;
+    S.settled += F.settled;
+    S.arcs += F.arcs;
+    S.early_trees += F.early_trees;
+    S.launches += F.launches;
+    S.kernel_launches += F.kernel_launches;
+    S.tree_ms += F.tree_ms;
+    S.prefix_ms += F.prefix_ms;
+    S.kernel_ms += F.kernel_ms;
+    S.assemble_ms += F.assemble_ms;
+    S.prep_ms += F.prep_ms;
+    S.tune_ms += F.tune_ms;
+    // per-root statistics are not kept for a directed labeling
+    if (bwd->per_root) {
+        bwd->alloc.free(bwd->per_root, bwd->alloc.ctx);
+        bwd->per_root = nullptr;
+    }
+    chl_labels_free(fwd);
+    *out = bwd;
+    return CHL_OK;
 }

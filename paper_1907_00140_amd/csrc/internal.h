@@ -104,6 +104,12 @@ int launch_rank_degrees(int32_t n, const int64_t* row_ptr, const int32_t* order,
                         hipStream_t st);
 int launch_check_symmetric(int32_t n, int64_t m, const int64_t* rrow, const uint64_t* rarc,
                            int32_t* err, hipStream_t st);
+// prep.hip: the reversed graph of a validated CSR (input ids): trow[n+1],
+// tcol/tw[m], each row sorted by (neighbour, weight); cnt[n], cursor[n],
+// tkey[m] and scan_temp (scan_temp_bytes(n)) are scratch
+int launch_transpose(int32_t n, int64_t m, const int64_t* row, const int32_t* col, const int32_t* w,
+                     int32_t* cnt, int64_t* trow, unsigned long long* cursor, uint64_t* tkey,
+                     int32_t* tcol, int32_t* tw, void* scan_temp, hipStream_t st);
 // out[64]: 16 samples x (row offset, ranking entry, neighbour, weight)
 int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const int32_t* w,
                         const int32_t* order, int64_t* out, hipStream_t st);
@@ -154,20 +160,30 @@ int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t us
 int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);
 constexpr int MAX_PREFIX = 4096;   // largest pruning prefix (root distances live in LDS)
 
-// query.hip
-int launch_query(int32_t n, const int64_t* offsets, const int32_t* hub_pos, const int32_t* dist,
+// query.hip: d(u, v) from the lists of u in (off_u, hub_u, dist_u) and of v
+// in (off_v, hub_v, dist_v) (the same arrays for an undirected labeling;
+// out- and in-labels for a directed one)
+int launch_query(int32_t n, const int64_t* off_u, const int32_t* hub_u, const int32_t* dist_u,
+                 const int64_t* off_v, const int32_t* hub_v, const int32_t* dist_v,
                  const int32_t* pairs, int64_t q, int64_t* out, int32_t* err, double avg_len,
                  hipStream_t st);
 
 }  // namespace chl
 
-// Device-resident labeling behind the opaque handle of the C-ABI.
+// Device-resident labeling behind the opaque handle of the C-ABI. For a
+// directed graph offsets/hub_pos/dist hold the out-labels and in_* the
+// in-labels.
 struct chl_labels {
     int32_t n = 0;
     int64_t total = 0;
     int64_t* offsets = nullptr;   // [n+1], by input id
     int32_t* hub_pos = nullptr;   // [total]
     int32_t* dist = nullptr;      // [total]
+    int directed = 0;
+    int64_t in_total = 0;
+    int64_t* in_offsets = nullptr;
+    int32_t* in_hub_pos = nullptr;
+    int32_t* in_dist = nullptr;
     int32_t* order = nullptr;     // [n] = hub_vertex
     int64_t* per_root = nullptr;  // [n][4] or null
     int32_t* qerr = nullptr;      // query error word

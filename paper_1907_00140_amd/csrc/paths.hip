@@ -329,7 +329,7 @@ using namespace chl;
 
 extern "C" int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32_t* parent, int32_t* slot,
                                   void* stream) {
-    if (!h || !g || g->n != h->n || g->n_arcs < 0 || !g->row_ptr) return CHL_ERR_INVALID_ARG;
+    if (!h || !g || h->directed || g->n != h->n || g->n_arcs < 0 || !g->row_ptr) return CHL_ERR_INVALID_ARG;
     if (g->n_arcs > 0 && (!g->col || !g->w)) return CHL_ERR_INVALID_ARG;
     if (h->total > 0 && (!parent || !slot)) return CHL_ERR_INVALID_ARG;
     if (h->total == 0 || h->n == 0) return CHL_OK;
@@ -352,7 +352,7 @@ extern "C" int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32
 extern "C" int chl_query_path_hops(const chl_labels* h, const int32_t* parent, const int32_t* slot,
                                    const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
                                    void* stream) {
-    if (!h || q < 0 || (q > 0 && (!pairs || !hops || !parent || !slot))) return CHL_ERR_INVALID_ARG;
+    if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !hops || !parent || !slot))) return CHL_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (q == 0) {
         if (path_off && hipMemsetAsync(path_off, 0, 8, st) != hipSuccess) return CHL_ERR_HIP;
@@ -387,7 +387,7 @@ extern "C" int chl_query_path_hops(const chl_labels* h, const int32_t* parent, c
 extern "C" int chl_query_paths(const chl_labels* h, const int32_t* parent, const int32_t* slot,
                                const int32_t* pairs, int64_t q, const int64_t* path_off, int32_t* path,
                                void* stream) {
-    if (!h || q < 0 || (q > 0 && (!pairs || !parent || !slot || !path_off))) return CHL_ERR_INVALID_ARG;
+    if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !parent || !slot || !path_off))) return CHL_ERR_INVALID_ARG;
     if (q == 0) return CHL_OK;
     hipStream_t st = (hipStream_t)stream;
     return with_err(h, st, [&]() {

@@ -119,6 +119,36 @@ __global__ void k_sym(int32_t n, int64_t m, const int64_t* __restrict__ rrow, co
     if (bad) atomicOr(err, ERR_BIT_INVALID);
 }
 
+// reversed graph: in-degree counts, then one wave per row scatters its
+// arcs v -> u as (v << 32) | w into row u (positions from a per-row cursor),
+// a segmented sort orders each row, and k_tsplit unpacks the words
+__global__ void k_indeg(int64_t m, const int32_t* __restrict__ col, int32_t* __restrict__ cnt) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[e]], 1);
+}
+
+__global__ void k_tscatter(int32_t n, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                           const int32_t* __restrict__ w, unsigned long long* __restrict__ cursor,
+                           uint64_t* __restrict__ tkey) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t v = wave; v < n; v += nwaves)
+        for (int64_t e = row[v] + lane; e < row[v + 1]; e += 64) {
+            const unsigned long long p = atomicAdd(&cursor[col[e]], 1ull);
+            tkey[p] = ((uint64_t)(uint32_t)v << 32) | (uint32_t)w[e];
+        }
+}
+
+__global__ void k_tsplit(int64_t m, const uint64_t* __restrict__ tkey, int32_t* __restrict__ tcol,
+                         int32_t* __restrict__ tw) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = tkey[e];
+        tcol[e] = (int32_t)(k >> 32);
+        tw[e] = (int32_t)(uint32_t)k;
+    }
+}
+
 int grid_for(int64_t work, int block) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -174,6 +204,22 @@ int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int3
                         const int32_t* order, int64_t* out, hipStream_t st) {
     if (n <= 0) return -1;
     hipLaunchKernelGGL(k_sample, dim3(1), dim3(64), 0, st, n, m, row_ptr, col, w, order, out);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_transpose(int32_t n, int64_t m, const int64_t* row, const int32_t* col, const int32_t* w,
+                     int32_t* cnt, int64_t* trow, unsigned long long* cursor, uint64_t* tkey,
+                     int32_t* tcol, int32_t* tw, void* scan_temp, hipStream_t st) {
+    if (hipMemsetAsync(cnt, 0, (size_t)n * 4, st) != hipSuccess) return -1;
+    if (m > 0) hipLaunchKernelGGL(k_indeg, dim3(grid_for(m, 256)), dim3(256), 0, st, m, col, cnt);
+    if (launch_scan_i32_to_i64(cnt, trow, n, scan_temp, st)) return -1;
+    if (hipMemcpyAsync(cursor, trow, (size_t)n * 8, hipMemcpyDeviceToDevice, st) != hipSuccess) return -1;
+    if (m > 0) {
+        hipLaunchKernelGGL(k_tscatter, dim3(grid_for((int64_t)n * 64, 256)), dim3(256), 0, st, n, row, col, w,
+                           cursor, tkey);
+        if (launch_segsort_u64(tkey, trow, n, m, nullptr, st)) return -1;
+        hipLaunchKernelGGL(k_tsplit, dim3(grid_for(m, 256)), dim3(256), 0, st, m, tkey, tcol, tw);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

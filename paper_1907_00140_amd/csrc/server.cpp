@@ -251,8 +251,10 @@ void chl_server::dispatch_loop() {
                     L = graphs[qblocks[sg.first].gid];
                 }
                 double avg = L->n ? (double)L->total / L->n : 1.0;
-                chl::launch_query(L->n, L->offsets, L->hub_pos, L->dist, B.d_pairs + 2 * off, sg.second,
-                                  B.d_out + off, d_err, avg, qs);
+                const bool dir = L->directed != 0;
+                chl::launch_query(L->n, L->offsets, L->hub_pos, L->dist, dir ? L->in_offsets : L->offsets,
+                                  dir ? L->in_hub_pos : L->hub_pos, dir ? L->in_dist : L->dist,
+                                  B.d_pairs + 2 * off, sg.second, B.d_out + off, d_err, avg, qs);
                 off += sg.second;
             }
             (void)hipMemcpyAsync(B.h_out, B.d_out, (size_t)fill * 8, hipMemcpyDeviceToHost, qs);
