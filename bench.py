@@ -198,6 +198,57 @@ def paths_measure(chl, L, c, d, pairs, stream, reps=3):
     return r
 
 
+def directed_measure(chl, gg, stream, reps=3):
+    """Directed R-MAT scale 16 (the generator's samples read as arcs): the
+    complete out- and in-labels (chl_build_directed, no rank-prefix pruning)
+    timed after one untimed build that tunes, and 10^6 queries. GTEPS = arcs
+    scanned by the oracle's early-terminating trees in both directions
+    (tests/golden/workload_counts.json) / build time."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    name = "rmat16dir"
+    c = gg.make_config(name)
+    d = [torch.from_numpy(c[f]).to(dev) for f in ("row_ptr", "col", "w", "order")]
+    pairs = torch.from_numpy(c["pairs"]).to(dev)
+    L = chl.build(*d, directed=True, stream=stream)
+    torch.cuda.synchronize()
+    L.free()
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L = chl.build(*d, directed=True, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        st = L.stats()
+        if len(times) < reps:
+            L.free()
+    qo = L.query(pairs, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.query(pairs, out=qo, stream=stream)
+    torch.cuda.synchronize()
+    qs = len(c["pairs"]) / (time.perf_counter() - t1)
+    L.free()
+    b = float(np.median(times))
+    wc = json.load(open(COUNTS)).get(name, {})
+    r = {"workload": "directed R-MAT scale 16 (65,536 vertices, %d arcs), int32 weights [1,1000], "
+                     "total-degree rank; out- and in-labels + 10^6 uniform queries" % c["m"],
+         "build_s": round(b, 4), "build_s_runs": [round(t, 4) for t in times], "labels": st["labels"],
+         "gpu_arcs": st["arcs"], "queries_per_s": round(qs, 1),
+         "roots_in_flight": st["roots_in_flight"], "wg_size": st["wg_size"], "delta": st["delta"],
+         "phases_ms": {"prep": round(st["prep_ms"], 2), "trees": round(st["tree_ms"], 2),
+                       "assemble": round(st["assemble_ms"], 2)}}
+    if "arcs" in wc:
+        r["gteps"] = round(wc["arcs"] / b / 1e9, 4)
+        r["oracle_arcs"] = wc["arcs"]
+        r["work_inflation"] = round(st["arcs"] / wc["arcs"], 3)
+        assert st["labels"] == wc["labels"], "label count differs from the oracle's"
+    print("directed:", json.dumps(r), file=sys.stderr, flush=True)
+    return r
+
+
 def large_workloads(chl, gg, stream):
     """The other workloads: the 64x64 grid (10^4 queries), the 1024x1024 grid
     with 5% diagonal shortcuts and R-MAT scale 20 (10^6 queries each). Full
@@ -292,6 +343,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-form estimate")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-directed", action="store_true", help="skip the directed-graph measurement")
     ap.add_argument("--large", action="store_true",
                     help="also build the other workloads (64x64 grid, 1024x1024 diagonal grid, R-MAT 20) "
                          "and report them in a 'large' object")
@@ -406,6 +458,8 @@ def main():
     paths = paths_measure(chl, L, c, (row, col, w), pairs, stream)
     L.free()
 
+    directed = None if args.no_directed else directed_measure(chl, gg, stream)
+
     # the same batched build without the common label table (PLaNT trees
     # alone, Section 4.2), for reference
     torch.cuda.synchronize()
@@ -493,6 +547,7 @@ def main():
                       "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
         "roofline": roofline, "cpu_baseline": cpu,
         "paths": paths,
+        "directed": directed,
     }
     if serving_full is not None:
         out["serving_full"] = serving_full

@@ -168,13 +168,18 @@ int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* op
  * (h, d(h, v)) such that h tops every shortest h -> v path (trees grown along
  * the arcs). chl_query answers d(u, v) = min over hubs common to L_out(u) and
  * L_in(v) of d(u, h) + d(h, v); chl_labels_info and chl_labels_export give
- * L_out, chl_labels_export_in gives L_in. The options apply to both builds
- * except prune_hubs, which is ignored (rank-prefix pruning is off: its test
- * would need both label sets of the prefix). Per-root statistics are not
- * kept (chl_build_stats with per_root != NULL returns CHL_ERR_INVALID_ARG);
- * the totals add up both builds. chl_labels_parents and the path queries
- * return CHL_ERR_INVALID_ARG on a directed handle. Synchronises `stream`.
- * Errors as for chl_build. */
+ * L_out, chl_labels_export_in gives L_in. Both sets come from one build over
+ * a combined graph of 2n vertices, the graph and its reversal, with the
+ * ranking interleaved (v at rank position 2 pos(v), its reversed copy at
+ * 2 pos(v) + 1); the options apply to that build, so roots_in_flight,
+ * prune_hubs, root_begin/count/stride and the statistics' prune_hubs and
+ * prefix_roots count in its rank positions (two per vertex), and the
+ * rank-prefix pruning (Section 4.3) takes d(h, x) from the out-labels and
+ * d(x, u) from the in-labels of the prefix. Per-root statistics are not
+ * kept (chl_build_stats with per_root != NULL returns CHL_ERR_INVALID_ARG).
+ * chl_labels_parents and the path queries return CHL_ERR_INVALID_ARG on a
+ * directed handle. Requires n <= 2^30 - 2 and n_arcs <= 2^31 - 1.
+ * Synchronises `stream`. Errors as for chl_build. */
 int chl_build_directed(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
                        const chl_allocator* alloc, void* stream, chl_labels** out);
 

@@ -5,6 +5,7 @@ the build (used for GTEPS and the roofline's algorithmic bytes). Calls only
 the oracle and the input generators.
 
 Usage: python -m oracle.workload_counts [--pruned-only | --no-levels] [name ...]
+(directed workloads, e.g. rmat16dir: both directions, unpruned)
 (--pruned-only skips the unpruned trees, whose count takes hours on the
 million-vertex R-MAT graph; --no-levels skips the pruned trees, which the
 build does not use on grids and whose prefix queries over grid-sized label
@@ -49,6 +50,22 @@ def level_bounds(labels_per_root, gmax):
         lv.append(g2)
         g = g2
     return lv
+
+
+def counts_directed(name, threads=None):
+    """Directed workloads: the unpruned early-terminating trees of every root
+    along the arcs (in-labels) and on the reversed graph (out-labels); the
+    totals add both ("in" and "out" keep each)."""
+    c = gg.make_config(name)
+    n = int(c["n"])
+    out = {"n": n, "m": int(c["m"]), "threads": threads or min(16, os.cpu_count() or 1), "directed": True}
+    t = time.time()
+    lo, li = oracle.chl_directed(c["row_ptr"], c["col"], c["w"], c["order"], threads=threads)
+    out["oracle_s"] = round(time.time() - t, 2)
+    out["out"], out["in"] = _sums(lo.stats, 0, n), _sums(li.stats, 0, n)
+    for k in ("arcs", "settled", "labels", "early_trees"):
+        out[k] = out["out"][k] + out["in"][k]
+    return out
 
 
 def counts(name, threads=None, pruned_only=False, levels=True):
@@ -98,6 +115,9 @@ if __name__ == "__main__":
     names = [a for a in args if not a.startswith("--")] or ["grid64", "rmat16"]
     data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for nm in names:
-        data[nm] = counts(nm, pruned_only=pruned_only, levels=levels)
+        if gg.make_config(nm).get("directed"):
+            data[nm] = counts_directed(nm)
+        else:
+            data[nm] = counts(nm, pruned_only=pruned_only, levels=levels)
         print(nm, data[nm], flush=True)
     json.dump(data, open(OUT, "w"), indent=1, sort_keys=True)

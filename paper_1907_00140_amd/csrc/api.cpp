@@ -179,6 +179,7 @@ struct Build {
     const int64_t* poff = nullptr;
     const uint64_t* plab = nullptr;
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
+    int32_t partner = 0;                 // combined graph of a directed build (TreeParams::partner)
     unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
     int32_t grown = 0;                   // roots [0, grown) done before the main phase
     double kernel_ms = 0;                // event-timed production tree launches
@@ -263,6 +264,7 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.poff = B.poff;
     p.plab = B.plab;
     p.pbound = B.pbound;
+    p.partner = B.partner;
     return p;
 }
 
@@ -765,6 +767,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     Build B;
     B.n = g->n;
     B.m = g->n_arcs;
+    B.partner = directed ? 1 : 0;
     const int32_t n = g->n;
     chl_stats S{};
     S.n = n;
@@ -1099,75 +1102,110 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
 // Directed graphs (footnote of Section 1): the trees grown along the arcs
 // give, at every vertex they reach clean, the in-label (h, d(h, v)); the
 // trees grown on the reversed graph give the out-label (h, d(v, h)). Both
-// are ordinary builds (the second on the reversed CSR, made on the device),
-// without the rank-prefix pruning, whose test would need the out-labels of
-// the prefix for the root and the in-labels for the vertex.
+// kinds are the trees of one build over a combined graph of 2n vertices: the
+// graph (ids [0, n)) and its reversal (ids [n, 2n)), two components, with the
+// ranking interleaved (v at rank position 2 pos(v), its reversed copy at
+// 2 pos(v) + 1), so that "u outranks h" keeps its meaning inside each
+// component, and every level of the rank-prefix pruning holds both trees of
+// its vertices. The pruning test needs d(h, x) + d(x, u) for a tree along the
+// arcs: d(x, u) is u's in-label from x, and d(h, x) the out-label of h from
+// x, i.e. the label of h's reversed copy from x's reversed copy, the partner
+// positions (TreeParams::partner).
 static int chl_build_directed_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
                                    const chl_allocator* alloc_in, void* stream, chl_labels** out) {
     if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
-    chl_build_opts o;
-    chl_build_opts_default(&o);
-    if (opts_in) o = *opts_in;
-    if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
-    o.prune_hubs = -1;
-    chl_labels* fwd = nullptr;
-    if (int r = chl_build_impl(g, order, &o, alloc_in, stream, &fwd, true)) return r;   // validates g
+    if (g->n < 1 || g->n > 0x3FFFFFFE || g->n_arcs < 0 || g->n_arcs > 0x7FFFFFFFll) return CHL_ERR_INVALID_ARG;
+    if (!g->row_ptr || (g->n_arcs > 0 && (!g->col || !g->w))) return CHL_ERR_INVALID_ARG;
+    if (int r = check_device()) return r;
     chl_allocator al = alloc_in ? *alloc_in : kDefaultAlloc;
+    if (!al.alloc || !al.free) return CHL_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     const int32_t n = g->n;
     const int64_t m = g->n_arcs;
-    int r = CHL_OK;
-    chl_labels* bwd = nullptr;
+    chl_labels* L = nullptr;
     {
         Arena A(al);
+        // validate the graph and the ranking before any kernel indexes with them
+        int32_t* ctl = A.get<int32_t>(16);
+        int32_t* pos = A.get<int32_t>(n);
         int32_t* cnt = A.get<int32_t>(n);
+        if (A.oom) return CHL_ERR_OOM;
+        HIPCHK(hipMemsetAsync(ctl, 0, 64, st));
+        HIPCHK(hipMemsetAsync(cnt, 0, (size_t)n * 4, st));
+        if (launch_validate(n, m, g->row_ptr, g->col, g->w, order, pos, cnt, ctl, ctl + 1, st)) return CHL_ERR_HIP;
+        HostCtl* hc = host_ctl();
+        if (!hc) return CHL_ERR_HIP;
+        HIPCHK(hipMemcpyAsync(hc->c32, ctl, 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (hc->c32[0]) return CHL_ERR_INVALID_ARG;
+        A.drop(pos);
+        // the reversed graph, then the combined graph
         int64_t* trow = A.get<int64_t>((size_t)n + 1);
         auto* cursor = A.get<unsigned long long>(n);
         uint64_t* tkey = A.get<uint64_t>((size_t)std::max<int64_t>(m, 1));
         int32_t* tcol = A.get<int32_t>((size_t)std::max<int64_t>(m, 1));
         int32_t* tw = A.get<int32_t>((size_t)std::max<int64_t>(m, 1));
         void* tmp = A.get<uint8_t>(scan_temp_bytes(std::max<int64_t>(n, 1)));
-        if (A.oom) r = CHL_ERR_OOM;
-        else if (launch_transpose(n, m, g->row_ptr, g->col, g->w, cnt, trow, cursor, tkey, tcol, tw, tmp, st))
+        int64_t* row2 = A.get<int64_t>(2 * (size_t)n + 1);
+        int32_t* col2 = A.get<int32_t>((size_t)std::max<int64_t>(2 * m, 1));
+        int32_t* w2 = A.get<int32_t>((size_t)std::max<int64_t>(2 * m, 1));
+        int32_t* order2 = A.get<int32_t>(2 * (size_t)n);
+        if (A.oom) return CHL_ERR_OOM;
+        if (launch_transpose(n, m, g->row_ptr, g->col, g->w, cnt, trow, cursor, tkey, tcol, tw, tmp, st) ||
+            launch_directed_union(n, m, g->row_ptr, g->col, g->w, order, trow, tcol, tw, row2, col2, w2, order2, st))
+            return CHL_ERR_HIP;
+        chl_graph g2{2 * n, 2 * m, row2, col2, w2};
+        int r = chl_build_impl(&g2, order2, opts_in, alloc_in, stream, &L, true);
+        HIPCHK(hipStreamSynchronize(st));   // the arena's buffers are released next
+        if (r) return r;
+    }
+    // split the combined labeling: in-labels in place, out-labels copied out
+    Arena keep(al);
+    int64_t tin = 0;
+    int64_t* out_off = nullptr;
+    int32_t *out_hub = nullptr, *out_dist = nullptr, *ord = nullptr;
+    int r = CHL_OK;
+    HostCtl* hc = host_ctl();
+    if (!hc || hipMemcpyAsync(hc->c64, L->offsets + n, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        r = CHL_ERR_HIP;
+    } else {
+        tin = (int64_t)hc->c64[0];
+        const int64_t tout = L->total - tin;
+        out_off = keep.get<int64_t>((size_t)n + 1);
+        out_hub = keep.get<int32_t>((size_t)std::max<int64_t>(tout, 1));
+        out_dist = keep.get<int32_t>((size_t)std::max<int64_t>(tout, 1));
+        ord = keep.get<int32_t>(n);
+        if (keep.oom) r = CHL_ERR_OOM;
+        else if (launch_directed_split(n, L->total, L->offsets, L->hub_pos, L->dist, out_off, out_hub, out_dist, st) ||
+                 hipMemcpyAsync(ord, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+                 hipStreamSynchronize(st) != hipSuccess)
             r = CHL_ERR_HIP;
-        if (!r) {
-            chl_graph gt{n, m, trow, tcol, tw};
-            r = chl_build_impl(&gt, order, &o, alloc_in, stream, &bwd, true);
-        }
-        if (hipStreamSynchronize(st) != hipSuccess && !r) r = CHL_ERR_HIP;
     }
     if (r) {
-        chl_labels_free(fwd);
+        chl_labels_free(L);
         return r;
     }
-    bwd->directed = 1;
-    bwd->in_total = fwd->total;
-    bwd->in_offsets = fwd->offsets;
-    bwd->in_hub_pos = fwd->hub_pos;
-    bwd->in_dist = fwd->dist;
-    fwd->offsets = nullptr;
-    fwd->hub_pos = nullptr;
-    fwd->dist = nullptr;
-    chl_stats& S = bwd->st;
-    const chl_stats& F = fwd->st;
-    S.labels += F.labels;
-    S.settled += F.settled;
-    S.arcs += F.arcs;
-    S.early_trees += F.early_trees;
-    S.launches += F.launches;
-    S.kernel_launches += F.kernel_launches;
-    S.tree_ms += F.tree_ms;
-    S.prefix_ms += F.prefix_ms;
-    S.kernel_ms += F.kernel_ms;
-    S.assemble_ms += F.assemble_ms;
-    S.prep_ms += F.prep_ms;
-    S.tune_ms += F.tune_ms;
-    // per-root statistics are not kept for a directed labeling
-    if (bwd->per_root) {
-        bwd->alloc.free(bwd->per_root, bwd->alloc.ctx);
-        bwd->per_root = nullptr;
-    }
-    chl_labels_free(fwd);
-    *out = bwd;
+    auto f = [&](void* p) { if (p) L->alloc.free(p, L->alloc.ctx); };
+    L->directed = 1;
+    L->in_total = tin;
+    L->in_offsets = L->offsets;     // the first n + 1 of the 2n + 1 offsets
+    L->in_hub_pos = L->hub_pos;
+    L->in_dist = L->dist;
+    L->offsets = out_off;
+    L->hub_pos = out_hub;
+    L->dist = out_dist;
+    L->total -= tin;
+    f(L->order);
+    L->order = ord;
+    f(L->per_root);                 // per-root statistics are not kept for a directed labeling
+    L->per_root = nullptr;
+    L->n = n;
+    L->st.n = n;
+    keep.release(out_off);
+    keep.release(out_hub);
+    keep.release(out_dist);
+    keep.release(ord);
+    *out = L;
     return CHL_OK;
 }

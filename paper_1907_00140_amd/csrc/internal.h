@@ -87,6 +87,11 @@ struct TreeParams {
     const int64_t* poff;
     const uint64_t* plab;
     int32_t pbound;
+    // 1 for the combined graph of a directed build (the graph's vertices at
+    // even rank positions 2i, their reversed copies at 2i + 1): a root's
+    // distances to the prefix hubs are those of its partner h ^ 1 from the
+    // hubs x ^ 1, d(h, x) being d'(x ^ 1, h ^ 1) on the reversed copy; 0 else
+    int32_t partner;
     // outputs
     int64_t* stats;         // [n][STAT_COLS] by root or NULL
     int32_t* err;
@@ -110,6 +115,15 @@ int launch_check_symmetric(int32_t n, int64_t m, const int64_t* rrow, const uint
 int launch_transpose(int32_t n, int64_t m, const int64_t* row, const int32_t* col, const int32_t* w,
                      int32_t* cnt, int64_t* trow, unsigned long long* cursor, uint64_t* tkey,
                      int32_t* tcol, int32_t* tw, void* scan_temp, hipStream_t st);
+// prep.hip: the combined graph of a directed build (2n vertices: the graph
+// and its reversal, ranks interleaved), and the split of its labeling into
+// in-labels (in place in hub2/dist2, hub positions halved) and out-labels
+// (out_off[n+1], out_hub / out_dist[total - off2[n]])
+int launch_directed_union(int32_t n, int64_t m, const int64_t* row, const int32_t* col, const int32_t* w,
+                          const int32_t* order, const int64_t* trow, const int32_t* tcol, const int32_t* tw,
+                          int64_t* row2, int32_t* col2, int32_t* w2, int32_t* order2, hipStream_t st);
+int launch_directed_split(int32_t n, int64_t total, const int64_t* off2, int32_t* hub2, const int32_t* dist2,
+                          int64_t* out_off, int32_t* out_hub, int32_t* out_dist, hipStream_t st);
 // out[64]: 16 samples x (row offset, ranking entry, neighbour, weight)
 int launch_sample_input(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const int32_t* w,
                         const int32_t* order, int64_t* out, hipStream_t st);

@@ -9,6 +9,8 @@
 // 8-byte load.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace chl {
 
 namespace {
@@ -149,6 +151,54 @@ __global__ void k_tsplit(int64_t m, const uint64_t* __restrict__ tkey, int32_t* 
     }
 }
 
+// combined graph of a directed build: vertices [0, n) are the graph's,
+// [n, 2n) their reversed copies (row n + v = the reversed row v, its
+// neighbours shifted by n); ranking interleaved, order2[2i] = order[i],
+// order2[2i + 1] = order[i] + n
+__global__ void k_dunion(int32_t n, int64_t m, const int64_t* __restrict__ row, const int32_t* __restrict__ col,
+                         const int32_t* __restrict__ w, const int32_t* __restrict__ order,
+                         const int64_t* __restrict__ trow, const int32_t* __restrict__ tcol,
+                         const int32_t* __restrict__ tw, int64_t* __restrict__ row2, int32_t* __restrict__ col2,
+                         int32_t* __restrict__ w2, int32_t* __restrict__ order2) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t v = t0; v <= n; v += stride) {
+        row2[v] = row[v];
+        row2[n + v] = m + trow[v];
+    }
+    for (int64_t v = t0; v < n; v += stride) {
+        order2[2 * v] = order[v];
+        order2[2 * v + 1] = order[v] + n;
+    }
+    for (int64_t e = t0; e < m; e += stride) {
+        col2[e] = col[e];
+        w2[e] = w[e];
+        col2[m + e] = tcol[e] + n;
+        w2[m + e] = tw[e];
+    }
+}
+
+// labels of the combined graph back to the two sets: in-labels are those of
+// vertices [0, n) (kept in place, hub positions halved), out-labels those of
+// [n, 2n) (copied out, hub positions halved)
+__global__ void k_dsplit(int32_t n, const int64_t* __restrict__ off2, int32_t* __restrict__ hub2,
+                         const int32_t* __restrict__ dist2, int64_t* __restrict__ out_off,
+                         int32_t* __restrict__ out_hub, int32_t* __restrict__ out_dist) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tin = off2[n], tall = off2[2 * (int64_t)n];
+    for (int64_t v = t0; v <= n; v += stride) out_off[v] = off2[n + v] - tin;
+    for (int64_t i = t0; i < tall; i += stride) {
+        const int32_t hp = hub2[i] >> 1;
+        if (i < tin) {
+            hub2[i] = hp;
+        } else {
+            out_hub[i - tin] = hp;
+            out_dist[i - tin] = dist2[i];
+        }
+    }
+}
+
 int grid_for(int64_t work, int block) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -220,6 +270,21 @@ int launch_transpose(int32_t n, int64_t m, const int64_t* row, const int32_t* co
         if (launch_segsort_u64(tkey, trow, n, m, nullptr, st)) return -1;
         hipLaunchKernelGGL(k_tsplit, dim3(grid_for(m, 256)), dim3(256), 0, st, m, tkey, tcol, tw);
     }
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_directed_union(int32_t n, int64_t m, const int64_t* row, const int32_t* col, const int32_t* w,
+                          const int32_t* order, const int64_t* trow, const int32_t* tcol, const int32_t* tw,
+                          int64_t* row2, int32_t* col2, int32_t* w2, int32_t* order2, hipStream_t st) {
+    hipLaunchKernelGGL(k_dunion, dim3(grid_for(std::max<int64_t>(m, (int64_t)n + 1), 256)), dim3(256), 0, st, n, m,
+                       row, col, w, order, trow, tcol, tw, row2, col2, w2, order2);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_directed_split(int32_t n, int64_t total, const int64_t* off2, int32_t* hub2, const int32_t* dist2,
+                          int64_t* out_off, int32_t* out_hub, int32_t* out_dist, hipStream_t st) {
+    hipLaunchKernelGGL(k_dsplit, dim3(grid_for(std::max<int64_t>(total, (int64_t)n + 1), 256)), dim3(256), 0, st,
+                       n, off2, hub2, dist2, out_off, out_hub, out_dist);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

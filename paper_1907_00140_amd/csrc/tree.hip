@@ -378,11 +378,13 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         const int32_t h = S.root;
         if (h < 0) break;
         const bool prune = PRUNE && h >= p.pbound;
+        const uint32_t px = (uint32_t)p.partner;
+        const int32_t hg = h ^ (int32_t)px;          // whose prefix labels give d(h, x)
         if (prune)
-            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
+            for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
-                const uint32_t x = (uint32_t)(lx >> 32);
-                if (x < (uint32_t)p.pbound) dh[x] = (uint32_t)lx;
+                const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = (uint32_t)lx;
             }
 
         // ---- init: root key (0, clean) in near list 0
@@ -541,9 +543,9 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         }
         // every read of dh is behind the emission's barriers
         if (prune)
-            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
-                const uint32_t x = (uint32_t)(p.plab[i] >> 32);
-                if (x < (uint32_t)p.pbound) dh[x] = 0xFFFFFFFFu;
+            for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
+                const uint32_t x = (uint32_t)(p.plab[i] >> 32), y = x ^ px;
+                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = 0xFFFFFFFFu;
             }
         __syncthreads();
     }
@@ -848,10 +850,12 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
         if (prune) {
             for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
             __syncthreads();
-            for (int64_t i = p.poff[h] + tid; i < p.poff[h + 1]; i += WG) {
+            const uint32_t px = (uint32_t)p.partner;
+            const int32_t hg = h ^ (int32_t)px;      // whose prefix labels give d(h, x)
+            for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
-                const uint32_t x = (uint32_t)(lx >> 32);
-                if (x < (uint32_t)p.pbound) dh[x] = (uint32_t)lx;
+                const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = (uint32_t)lx;
             }
             __syncthreads();
         }
