@@ -66,3 +66,16 @@ def test_product_does_not_reach_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "chl_oracle" not in txt, f
+
+
+def test_build_entry_resolves_the_build_module():
+    """__graft_entry__.build() compiles through paper_1907_00140_amd.build:
+    the package must not shadow that submodule with another object."""
+    import importlib
+    import types
+    import paper_1907_00140_amd as pkg
+    assert not callable(getattr(pkg, "build", None)) or isinstance(pkg.build, types.ModuleType)
+    b = importlib.import_module("paper_1907_00140_amd.build")
+    assert callable(b.build)
+    import __graft_entry__ as ge
+    assert callable(ge.build) and callable(ge.smoke)
