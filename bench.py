@@ -348,6 +348,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     ap.add_argument("--no-directed", action="store_true", help="skip the directed-graph measurement")
     ap.add_argument("--no-paths", action="store_true", help="skip the shortest-path measurement")
+    ap.add_argument("--no-atomic-ceiling", action="store_true", help="skip the atomic-minimum microbenchmark")
     ap.add_argument("--large", action="store_true",
                     help="also build the other workloads (64x64 grid, 1024x1024 diagonal grid, R-MAT 20) "
                          "and report them in a 'large' object")
@@ -466,6 +467,25 @@ def main():
 
     directed = None if args.no_directed else directed_measure(chl, gg, stream)
 
+    # ceiling of the relaxation's memory operation: random atomic minima on
+    # an array of the main phase's slot keys (roots in flight x n keys)
+    atomics = None
+    if not args.no_atomic_ceiling:
+        kb = int(stats["key_bits"])
+        words = int(stats["roots_in_flight"]) * c["n"]
+        chl.microbench_atomic_min(words, kb, ops=1 << 24)
+        rates = []
+        for _ in range(3):
+            done, ams = chl.microbench_atomic_min(words, kb, ops=1 << 28)
+            rates.append(done / (ams / 1e3))
+        build_kernel_s = per_launch_ms * nl / 1e3
+        relax = gpu_arcs / build_kernel_s
+        atomics = {"ceiling_atomic_min_per_s": round(max(rates), 1), "array_bytes": words * kb // 8, "key_bits": kb,
+                   "tree_relaxations_per_s": round(relax, 1), "frac": round(relax / max(rates), 5),
+                   "note": "relaxations = arcs relaxed by the tree kernels of one build (a key load and at most one "
+                           "atomic minimum each) / their summed launch time; ceiling = best of 3 runs of 2^28 random "
+                           "atomic minima (chl_microbench_atomic_min)"}
+
     # the same batched build without the common label table (PLaNT trees
     # alone, Section 4.2), for reference
     torch.cuda.synchronize()
@@ -551,7 +571,7 @@ def main():
         "work_inflation": round(gpu_arcs / max(1, units["arcs"]), 3),
         "phases_ms": {"prep": round(stats["prep_ms"], 3), "prefix": round(stats["prefix_ms"], 3),
                       "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "atomics": atomics, "cpu_baseline": cpu,
         "paths": paths,
         "directed": directed,
     }

@@ -306,6 +306,17 @@ int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root,
 /* Release a handle and its device memory (NULL is a no-op). */
 void chl_labels_free(chl_labels* h);
 
+/* ---- measurement ----
+ * Ceiling of the tree kernels' relaxation step (the atomic minimum on a
+ * packed key that realises Algorithm 3's distance and ancestor update):
+ * about `ops` random atomic minima (32- or 64-bit, key_bits) on the device
+ * array buf of `words` keys, which the call first sets to all ones. *done
+ * receives the number performed, *ms the device time (events on `stream`).
+ * buf is caller-owned device memory of words * key_bits / 8 bytes.
+ * Synchronises `stream`. */
+int chl_microbench_atomic_min(void* buf, int64_t words, int key_bits, int64_t ops, int64_t* done,
+                              double* ms, void* stream);
+
 /* ---- continuous-batching server ----
  * A host thread that owns device streams, keeps labelings resident, batches
  * distance queries that have arrived and admits build requests by their

@@ -26,7 +26,7 @@ FLAGS = [
     f"-I{INCLUDE}",
 ]
 SOURCES = ["api.cpp", "prep.hip", "scan.hip", "segsort.hip", "tree.hip", "assemble.hip",
-           "query.hip", "paths.hip", "server.cpp"]
+           "query.hip", "paths.hip", "microbench.hip", "server.cpp"]
 
 
 def _compile(src):

@@ -92,6 +92,7 @@ def load(path=LIB_PATH):
             "chl_labels_hub_vertex": (C.c_int, [vp, vp, C.c_int, vp]),
             "chl_query": (C.c_int, [vp, vp, i64, vp, vp]),
             "chl_labels_parents": (C.c_int, [vp, vp, vp, vp, vp]),
+            "chl_microbench_atomic_min": (C.c_int, [vp, i64, C.c_int, i64, vp, vp, vp]),
             "chl_query_path_hops": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "chl_query_paths": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "chl_build_stats": (C.c_int, [vp, vp, vp, C.c_int, vp]),
@@ -364,3 +365,13 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
              C.byref(out))
     _check(code, "chl_build_directed" if directed else "chl_build")
     return Labels(out.value, al)
+
+
+def microbench_atomic_min(words, key_bits=32, ops=1 << 28, stream=None):
+    """Random atomic minima on a device array of `words` keys: (ops done, ms)."""
+    lib = load()
+    buf = torch.empty(int(words) * (key_bits // 8), dtype=torch.uint8, device="cuda")
+    done, ms = C.c_int64(), C.c_double()
+    _check(lib.chl_microbench_atomic_min(buf.data_ptr(), int(words), int(key_bits), int(ops), C.byref(done),
+                                         C.byref(ms), _stream_ptr(stream)), "chl_microbench_atomic_min")
+    return done.value, ms.value

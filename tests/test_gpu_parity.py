@@ -320,3 +320,23 @@ def test_grid1024d_full_queries():
         q = L.query(pairs).cpu().numpy()
         assert np.array_equal(q, ref[tgt]), s
     L.free()
+
+
+def test_microbench_atomic_min():
+    """The measurement entry point runs, reports what it did, and leaves every
+    key at or below its all-ones start."""
+    import torch
+    from paper_1907_00140_amd import chl
+    lib = chl.load()
+    import ctypes as C
+    for kb in (32, 64):
+        words = 1 << 20
+        buf = torch.empty(words * kb // 8, dtype=torch.uint8, device="cuda")
+        done, ms = C.c_int64(), C.c_double()
+        rc = lib.chl_microbench_atomic_min(buf.data_ptr(), words, kb, 1 << 22, C.byref(done), C.byref(ms),
+                                           C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0 and done.value >= 1 << 21 and ms.value > 0
+        v = buf.view(torch.int32 if kb == 32 else torch.int64)
+        assert (v != -1).sum().item() > words // 2        # most keys were lowered
+    with pytest.raises(chl.ChlError):
+        chl.microbench_atomic_min(16, key_bits=16)
