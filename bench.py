@@ -359,7 +359,7 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(every tree is independent; see the sharding design in the docs)", file=sys.stderr)
         sys.exit(2)
 
@@ -467,6 +467,28 @@ def main():
 
     directed = None if args.no_directed else directed_measure(chl, gg, stream)
 
+    # end to end from host memory: upload of the CSR and the ranking, the
+    # build, and the labeling copied back to host memory (the timed steps
+    # above start with the inputs resident in HBM)
+    e2e = None
+    if not args.no_paths:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        hd = [torch.from_numpy(c[f]).to(dev) for f in ("row_ptr", "col", "w", "order")]
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        Le = chl.build(*hd, stream=stream)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        Le.export("cpu")
+        t4 = time.perf_counter()
+        Le.free()
+        del hd
+        e2e = {"upload_ms": round((t2 - t1) * 1e3, 3), "build_ms": round((t3 - t2) * 1e3, 3),
+               "download_ms": round((t4 - t3) * 1e3, 3), "total_ms": round((t4 - t1) * 1e3, 3),
+               "gteps_end_to_end": round(A / (t4 - t1) / 1e9, 4),
+               "note": "pageable host arrays (numpy) -> device, chl_build, chl_labels_export to host"}
+
     # ceiling of the relaxation's memory operation: random atomic minima on
     # an array of the main phase's slot keys (roots in flight x n keys)
     atomics = None
@@ -571,7 +593,7 @@ def main():
         "work_inflation": round(gpu_arcs / max(1, units["arcs"]), 3),
         "phases_ms": {"prep": round(stats["prep_ms"], 3), "prefix": round(stats["prefix_ms"], 3),
                       "main": round(stats["tree_ms"], 3), "assemble": round(stats["assemble_ms"], 3)},
-        "roofline": roofline, "atomics": atomics, "cpu_baseline": cpu,
+        "roofline": roofline, "atomics": atomics, "cpu_baseline": cpu, "end_to_end": e2e,
         "paths": paths,
         "directed": directed,
     }
