@@ -230,10 +230,12 @@ int chl_query(const chl_labels* h, const int32_t* pairs, int64_t q, int64_t* out
  * Compute the parents of every label of h: parent[total] and slot[total]
  * (int32, device, caller-owned, in the label order of chl_labels_export).
  * g must be the graph the labeling was built from (device CSR, input ids);
- * g->n must equal the labeling's n. Synchronises `stream`. Errors:
- * CHL_ERR_INVALID_ARG (NULL or mismatched arguments; an arc with a
- * neighbour outside [0, n) or a weight < 1, or a malformed row; such arcs
- * are skipped and the parents are then unspecified), CHL_ERR_HIP. */
+ * g->n must equal the labeling's n. Takes 256 bytes of scratch (a work
+ * queue counter) from the labeling's allocator. Synchronises `stream`.
+ * Errors: CHL_ERR_INVALID_ARG (NULL or mismatched arguments, a directed
+ * labeling; an arc with a neighbour outside [0, n) or a weight < 1, or a
+ * malformed row: such arcs are skipped and the parents are then
+ * unspecified), CHL_ERR_OOM, CHL_ERR_HIP. */
 int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32_t* parent, int32_t* slot,
                        void* stream);
 
