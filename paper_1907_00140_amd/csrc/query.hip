@@ -4,15 +4,117 @@
 // u's out-list and L_v v's in-list, footnote of Section 1). A group of G
 // lanes answers one query: each lane takes every G-th hub of the shorter
 // list and looks it up by binary search in the longer one (both lists are
-// sorted by hub rank position), then the group reduces the minimum.
+// sorted by hub rank position), then the group reduces the minimum. Large
+// batches over short lists first give each query one lane (k_query_tier).
 #include "internal.h"
 
 namespace chl {
 
 namespace {
 
+// Lower bound of hub x in hub[lo, hi).
+__device__ __forceinline__ int64_t lower_hub(const int32_t* __restrict__ hub, int64_t lo, int64_t hi, int32_t x) {
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (hub[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Two tiers in one pass. Every lane first takes one query of its wave's 64:
+// when the shorter list has at most SMALL entries (a vertex with only its
+// own label, frequent in scale-free graphs, or very few), the lane answers
+// it alone. The other queries of the 64 are then answered by groups of G
+// lanes of the same wave, a few at a time, their list bounds passed between
+// lanes by shuffles: every lane of a group takes every G-th hub of the
+// shorter list, searches it in the longer one, and the group reduces.
+constexpr int SMALL = 2;
+
 template <int G>
-__global__ __launch_bounds__(256) void k_query(int32_t n, const int64_t* __restrict__ off_u,
+__global__ __launch_bounds__(256) void k_query_tier(int32_t n, const int64_t* __restrict__ off_u,
+                                               const int32_t* __restrict__ hub_u,
+                                               const int32_t* __restrict__ dist_u,
+                                               const int64_t* __restrict__ off_v,
+                                               const int32_t* __restrict__ hub_v,
+                                               const int32_t* __restrict__ dist_v,
+                                               const int32_t* __restrict__ pairs, int64_t q,
+                                               int64_t* __restrict__ out, int32_t* err) {
+    constexpr int NSUB = 64 / G;
+    const int lane = threadIdx.x & 63, sub = lane / G, gl = lane & (G - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * 256) >> 6;
+    for (int64_t base = wave * 64; base < q; base += nwaves * 64) {
+        const int64_t k = base + lane;
+        bool big = false;
+        int64_t ab = 0, ae = 0, bb = 0, be = 0;
+        int swapped = 0;
+        if (k < q) {
+            const int32_t u = pairs[2 * k], v = pairs[2 * k + 1];
+            if (u >= 0 && u < n && v >= 0 && v < n) {
+                ab = off_u[u]; ae = off_u[u + 1]; bb = off_v[v]; be = off_v[v + 1];
+                if (ae - ab > be - bb) {
+                    int64_t t = ab; ab = bb; bb = t;
+                    t = ae; ae = be; be = t;
+                    swapped = 1;
+                }
+                if (ae - ab <= SMALL) {
+                    const int32_t *ha = swapped ? hub_v : hub_u, *da = swapped ? dist_v : dist_u;
+                    const int32_t *hb = swapped ? hub_u : hub_v, *db = swapped ? dist_u : dist_v;
+                    int64_t best = INT64_MAX;
+                    for (int64_t i = ab; i < ae; i++) {
+                        const int32_t x = ha[i];
+                        const int64_t lo = lower_hub(hb, bb, be, x);
+                        if (lo < be && hb[lo] == x) {
+                            const int64_t sum = (int64_t)da[i] + (int64_t)db[lo];
+                            best = sum < best ? sum : best;
+                        }
+                    }
+                    out[k] = best == INT64_MAX ? -1 : best;
+                } else {
+                    big = true;
+                }
+            } else {
+                atomicOr(err, ERR_BIT_INVALID);
+                out[k] = -2;
+            }
+        }
+        // the remaining queries of the wave, NSUB at a time, one per group
+        unsigned long long mask = __ballot(big);
+        while (mask) {
+            unsigned long long m = mask;
+            for (int j = 0; j < sub && m; j++) m &= m - 1;
+            const int src = m ? __ffsll((long long)m) - 1 : 0;
+            const bool has = m != 0;
+            const int64_t gab = __shfl(ab, src), gae = __shfl(ae, src);
+            const int64_t gbb = __shfl(bb, src), gbe = __shfl(be, src);
+            const int gsw = __shfl(swapped, src);
+            int64_t best = INT64_MAX;
+            if (has) {
+                const int32_t *ha = gsw ? hub_v : hub_u, *da = gsw ? dist_v : dist_u;
+                const int32_t *hb = gsw ? hub_u : hub_v, *db = gsw ? dist_u : dist_v;
+                for (int64_t i = gab + gl; i < gae; i += G) {
+                    const int32_t x = ha[i];
+                    const int64_t lo = lower_hub(hb, gbb, gbe, x);
+                    if (lo < gbe && hb[lo] == x) {
+                        const int64_t sum = (int64_t)da[i] + (int64_t)db[lo];
+                        best = sum < best ? sum : best;
+                    }
+                }
+            }
+#pragma unroll
+            for (int d = G / 2; d >= 1; d >>= 1) {
+                const int64_t o = __shfl_xor(best, d, G);
+                best = o < best ? o : best;
+            }
+            if (has && gl == 0) out[base + src] = best == INT64_MAX ? -1 : best;
+            for (int j = 0; j < NSUB && mask; j++) mask &= mask - 1;
+        }
+    }
+}
+
+// One group of G lanes per query (lists long on average, or few queries).
+template <int G>
+__global__ __launch_bounds__(256) void k_query_group(int32_t n, const int64_t* __restrict__ off_u,
                                                const int32_t* __restrict__ hub_u,
                                                const int32_t* __restrict__ dist_u,
                                                const int64_t* __restrict__ off_v,
@@ -66,16 +168,28 @@ int launch_query(int32_t n, const int64_t* off_u, const int32_t* hub_u, const in
                  const int32_t* pairs, int64_t q, int64_t* out, int32_t* err, double avg_len,
                  hipStream_t st) {
     if (q <= 0) return 0;
-    int G = avg_len <= 24 ? 8 : avg_len <= 96 ? 16 : avg_len <= 256 ? 32 : 64;
-    int64_t blocks = (q * G + 255) / 256;
+    const int G = avg_len <= 24 ? 8 : avg_len <= 96 ? 16 : avg_len <= 256 ? 32 : 64;
+    // the two-tier kernel for short lists and batches that fill the device
+    // with one wave per 64 queries; else one group per query
+    const bool tier = G <= 16 && q >= (1 << 16);
+    int64_t blocks = tier ? (q + 255) / 256 : (q * G + 255) / 256;
     if (blocks > 1 << 20) blocks = 1 << 20;
     if (blocks < 1) blocks = 1;
-    switch (G) {
-        case 8: hipLaunchKernelGGL(k_query<8>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, pairs, q, out, err); break;
-        case 16: hipLaunchKernelGGL(k_query<16>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, pairs, q, out, err); break;
-        case 32: hipLaunchKernelGGL(k_query<32>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, pairs, q, out, err); break;
-        default: hipLaunchKernelGGL(k_query<64>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, pairs, q, out, err); break;
+#define CHL_QUERY(KER, GG)                                                                                  \
+    hipLaunchKernelGGL(KER<GG>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, \
+                       pairs, q, out, err)
+    if (tier) {
+        if (G == 8) CHL_QUERY(k_query_tier, 8);
+        else CHL_QUERY(k_query_tier, 16);
+    } else {
+        switch (G) {
+            case 8: CHL_QUERY(k_query_group, 8); break;
+            case 16: CHL_QUERY(k_query_group, 16); break;
+            case 32: CHL_QUERY(k_query_group, 32); break;
+            default: CHL_QUERY(k_query_group, 64); break;
+        }
     }
+#undef CHL_QUERY
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
