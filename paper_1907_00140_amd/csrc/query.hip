@@ -5,7 +5,8 @@
 // lanes answers one query: each lane takes every G-th hub of the shorter
 // list and looks it up by binary search in the longer one (both lists are
 // sorted by hub rank position), then the group reduces the minimum. Large
-// batches over short lists first give each query one lane (k_query_tier).
+// batches over short lists first give each query one lane (k_query_tier);
+// long lists are staged in LDS (k_query_lds).
 #include "internal.h"
 
 namespace chl {
@@ -112,6 +113,97 @@ __global__ __launch_bounds__(256) void k_query_tier(int32_t n, const int64_t* __
     }
 }
 
+// Long lists (hundreds to thousands of labels, road-like graphs): one wave
+// per query. The shorter list's hubs are copied into the wave's LDS with
+// coalesced loads; the lanes then read the longer list 64 hubs at a time,
+// also coalesced, and look each up by binary search in LDS, so that global
+// memory sees each list once, in order, instead of a chain of dependent
+// loads per hub. A shorter list beyond QCAP hubs is searched in global
+// memory instead.
+constexpr int QCAP = 2560;   // 10 KB of LDS per wave: 16 waves per compute unit
+constexpr int QW = 4;        // waves per workgroup
+constexpr int QILP = 4;      // loads in flight per lane
+
+__global__ __launch_bounds__(64 * QW) void k_query_lds(int32_t n, const int64_t* __restrict__ off_u,
+                                                       const int32_t* __restrict__ hub_u,
+                                                       const int32_t* __restrict__ dist_u,
+                                                       const int64_t* __restrict__ off_v,
+                                                       const int32_t* __restrict__ hub_v,
+                                                       const int32_t* __restrict__ dist_v,
+                                                       const int32_t* __restrict__ pairs, int64_t q,
+                                                       int64_t* __restrict__ out, int32_t* err) {
+    __shared__ int32_t sh_all[QW][QCAP];
+    const int lane = threadIdx.x & 63;
+    int32_t* sh = sh_all[threadIdx.x >> 6];
+    const int64_t wave = ((int64_t)blockIdx.x * 64 * QW + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * 64 * QW) >> 6;
+    for (int64_t k = wave; k < q; k += nwaves) {
+        const int32_t u = pairs[2 * k], v = pairs[2 * k + 1];
+        const bool ok = u >= 0 && u < n && v >= 0 && v < n;
+        int64_t best = INT64_MAX;
+        if (ok) {
+            int64_t ab = off_u[u], ae = off_u[u + 1], bb = off_v[v], be = off_v[v + 1];
+            const int32_t *ha = hub_u, *da = dist_u, *hb = hub_v, *db = dist_v;
+            if (ae - ab > be - bb) {
+                int64_t t = ab; ab = bb; bb = t;
+                t = ae; ae = be; be = t;
+                ha = hub_v; da = dist_v; hb = hub_u; db = dist_u;
+            }
+            const int64_t la = ae - ab;
+            if (la <= QCAP) {
+                for (int64_t t0 = lane; t0 < la; t0 += 64 * QILP) {
+                    int32_t x[QILP];
+#pragma unroll
+                    for (int r = 0; r < QILP; r++) x[r] = t0 + r * 64 < la ? ha[ab + t0 + r * 64] : 0;
+#pragma unroll
+                    for (int r = 0; r < QILP; r++)
+                        if (t0 + r * 64 < la) sh[t0 + r * 64] = x[r];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                for (int64_t t0 = bb + lane; t0 < be; t0 += 64 * QILP) {
+                    int32_t x[QILP];
+#pragma unroll
+                    for (int r = 0; r < QILP; r++) x[r] = t0 + r * 64 < be ? hb[t0 + r * 64] : INT32_MAX;
+#pragma unroll
+                    for (int r = 0; r < QILP; r++) {
+                        int lo = 0, hi = (int)la;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (sh[mid] < x[r]) lo = mid + 1; else hi = mid;
+                        }
+                        if (t0 + r * 64 < be && lo < la && sh[lo] == x[r]) {
+                            const int64_t sum = (int64_t)da[ab + lo] + (int64_t)db[t0 + r * 64];
+                            best = sum < best ? sum : best;
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            } else {
+                for (int64_t i = ab + lane; i < ae; i += 64) {
+                    const int32_t x = ha[i];
+                    const int64_t lo = lower_hub(hb, bb, be, x);
+                    if (lo < be && hb[lo] == x) {
+                        const int64_t sum = (int64_t)da[i] + (int64_t)db[lo];
+                        best = sum < best ? sum : best;
+                    }
+                }
+            }
+        } else if (lane == 0) {
+            atomicOr(err, ERR_BIT_INVALID);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            const int64_t o = __shfl_xor(best, d);
+            best = o < best ? o : best;
+        }
+        if (lane == 0) out[k] = ok ? (best == INT64_MAX ? -1 : best) : -2;
+    }
+}
+
 // One group of G lanes per query (lists long on average, or few queries).
 template <int G>
 __global__ __launch_bounds__(256) void k_query_group(int32_t n, const int64_t* __restrict__ off_u,
@@ -181,16 +273,18 @@ int launch_query(int32_t n, const int64_t* off_u, const int32_t* hub_u, const in
 #define CHL_QUERY(KER, GG)                                                                                  \
     hipLaunchKernelGGL(KER<GG>, dim3(blocks), dim3(256), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v, dist_v, \
                        pairs, q, out, err)
-    if (tier) {
+    if (G >= 32) {
+        // one wave per query, the shorter list in LDS
+        int64_t wb = (q + QW - 1) / QW;
+        if (wb > 1 << 20) wb = 1 << 20;
+        hipLaunchKernelGGL(k_query_lds, dim3(wb), dim3(64 * QW), 0, st, n, off_u, hub_u, dist_u, off_v, hub_v,
+                           dist_v, pairs, q, out, err);
+    } else if (tier) {
         if (GT == 16) CHL_QUERY(k_query_tier, 16);
         else CHL_QUERY(k_query_tier, 32);
     } else {
-        switch (G) {
-            case 8: CHL_QUERY(k_query_group, 8); break;
-            case 16: CHL_QUERY(k_query_group, 16); break;
-            case 32: CHL_QUERY(k_query_group, 32); break;
-            default: CHL_QUERY(k_query_group, 64); break;
-        }
+        if (G == 8) CHL_QUERY(k_query_group, 8);
+        else CHL_QUERY(k_query_group, 16);
     }
 #undef CHL_QUERY
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -364,3 +364,27 @@ def test_query_tiers_rmat20():
         assert np.array_equal(q[i * 3500:(i + 1) * 3500], ref[tgt[i]]), int(s)
     parts = [L.query(torch.from_numpy(pairs[a:a + 30000]).cuda()).cpu().numpy() for a in range(0, len(pairs), 30000)]
     assert np.array_equal(np.concatenate(parts), q)
+
+
+def test_query_long_lists_complete_graph():
+    """K_3000 with unit weights (closed form: L_v = {(v, 0)} and (u, 1) for
+    every u ranked above v, so the lowest ranked vertices hold ~3000 labels):
+    label sizes, and queries between low-ranked vertices, whose lists exceed
+    the LDS stage of the long-list query kernel, equal 1 (0 when u = v)."""
+    from paper_1907_00140_amd import chl
+    n = 3000
+    row = np.arange(n + 1, dtype=np.int64) * (n - 1)
+    col = np.broadcast_to(np.arange(n, dtype=np.int32), (n, n))[~np.eye(n, dtype=bool)].copy()
+    w = np.ones(len(col), dtype=np.int32)
+    order = gg.random_rank(n, 5)
+    pos = pins.pos_of(order)
+    _say("complete graph", n)
+    L = chl.build(row, col, w, order)
+    off, hub, dist = (t.numpy() for t in L.export("cpu"))
+    assert np.array_equal(np.diff(off), pos + 1)
+    low = order[-400:]
+    g = np.random.default_rng(5)
+    pairs = np.stack([g.choice(low, 5000), g.choice(low, 5000)], 1).astype(np.int32)
+    pairs = np.concatenate([pairs, np.stack([g.integers(0, n, 5000), g.integers(0, n, 5000)], 1).astype(np.int32)])
+    q = L.query(pairs).cpu().numpy()
+    assert np.array_equal(q, (pairs[:, 0] != pairs[:, 1]).astype(np.int64))
