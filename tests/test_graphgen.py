@@ -67,3 +67,32 @@ def test_mix64_known_values():
     # splitmix64 output for state 0 and 1 (first output of the generator)
     assert int(gg.mix64(np.array([0], np.uint64))[0]) == 0xE220A8397B1DCDAF
     assert int(gg.mix64(np.array([1], np.uint64))[0]) == 0x910A2DEC89025CC1
+
+
+def test_directed_rmat():
+    """Directed R-MAT: the samples of the undirected generator read as arcs,
+    no self-loops, no duplicate arcs, not symmetric, rows sorted; the
+    reversed CSR holds the same arcs; the rank orders by total degree."""
+    c = gg.make_config("rmat12d9")
+    n, row, col, w = c["n"], c["row_ptr"], c["col"], c["w"]
+    assert c["directed"] and row[0] == 0 and row[-1] == len(col) == len(w) == c["m"]
+    src = np.repeat(np.arange(n), np.diff(row))
+    assert (col != src).all()
+    key = src.astype(np.int64) * n + col
+    assert (np.diff(key) > 0).all()                              # sorted, no duplicates
+    rev = col.astype(np.int64) * n + src
+    assert not np.array_equal(np.sort(key), np.sort(rev))       # genuinely directed
+    assert w.min() >= 1 and w.max() <= 1000
+    trow, tcol, tw = gg.transpose_csr(row, col, w)
+    tsrc = np.repeat(np.arange(n), np.diff(trow))
+    fwd = sorted(zip(src.tolist(), col.tolist(), w.tolist()))
+    back = sorted(zip(tcol.tolist(), tsrc.tolist(), tw.tolist()))
+    assert fwd == back
+    deg = np.diff(row) + np.bincount(col, minlength=n)
+    assert (np.diff(deg[c["order"]]) <= 0).all()
+    # same samples as the undirected generator of the same seed
+    n2, u2, v2, _ = gg.rmat_edges(12, 8, *gg.RMAT_ABC, 9, 1, 1000)
+    und = set(zip(u2.tolist(), v2.tolist()))
+    assert all((min(a, b), max(a, b)) in und for a, b in zip(src.tolist()[:2000], col.tolist()[:2000]))
+    d2 = gg.make_config("rmat12d9")
+    assert np.array_equal(d2["col"], col) and np.array_equal(d2["w"], w)
