@@ -248,6 +248,14 @@ def directed_measure(chl, gg, stream, reps=3):
         r["oracle_arcs"] = wc["arcs"]
         r["gpu_arcs_per_unpruned_oracle_arc"] = round(st["arcs"] / wc["arcs"], 4)
         assert st["labels"] == wc["labels"], "label count differs from the oracle's"
+    # the oracle's trees under the same pruning schedule on the combined graph
+    lv = next((v for v in wc.values() if isinstance(v, dict) and v.get("grown") == st["prefix_roots"]
+               and v.get("pmain") == st["prune_hubs"]), None)
+    if lv is not None:
+        a = lv["head"]["arcs"] + lv["rest"]["arcs"]
+        r["method_gteps"] = round(a / b / 1e9, 4)
+        r["oracle_arcs_method"] = a
+        r["work_inflation"] = round(st["arcs"] / a, 3)
     print("directed:", json.dumps(r), file=sys.stderr, flush=True)
     return r
 

@@ -53,7 +53,7 @@ def load(path=None):
     lib.oracle_run_roots.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, C.c_int, C.c_int]
     lib.oracle_run_roots_levels.restype = vp
     lib.oracle_run_roots_levels.argtypes = [C.c_int32, vp, vp, vp, vp, vp, C.c_int64, vp, C.c_int32,
-                                            C.c_int32, C.c_int]
+                                            C.c_int32, C.c_int32, C.c_int]
     lib.oracle_run_count.restype = C.c_int64
     lib.oracle_run_count.argtypes = [vp, C.c_int64]
     lib.oracle_run_total.restype = C.c_int64
@@ -137,13 +137,15 @@ def _assemble(lib, h, n):
 
 
 def chl_pruned(row_ptr, col, w, order, eta=None, grown=None, levels=None, pmain=None, threads=None,
-               lib=None):
+               lib=None, half=0):
     """Complete CHL by PLaNT trees with rank-prefix pruning (Section 4.3),
     grown in levels: ``levels`` = [g_0, g_1, ...]: roots [0, g_0) unpruned,
     level [g_{j-1}, g_j) pruned by the labels of hubs [0, g_{j-1}), and every
     later root pruned by hubs [0, pmain). ``eta, grown`` is the one-level
     case (levels=[grown], pmain=eta). Same labels as chl(); different work
-    counts (stats, indexed by root rank position)."""
+    counts (stats, indexed by root rank position). half > 0: the graph is the
+    combined graph of a directed graph (see combined_directed) with
+    half = its vertex count."""
     lib = lib or load()
     if levels is None:
         levels, pmain = [grown], eta
@@ -152,7 +154,8 @@ def chl_pruned(row_ptr, col, w, order, eta=None, grown=None, levels=None, pmain=
     lv = np.ascontiguousarray(levels, dtype=np.int32)
     threads = threads or min(16, os.cpu_count() or 1)
     h = lib.oracle_run_roots_levels(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
-                                    order.ctypes.data, None, 0, lv.ctypes.data, len(lv), int(pmain), threads)
+                                    order.ctypes.data, None, 0, lv.ctypes.data, len(lv), int(pmain), int(half),
+                                    threads)
     return _assemble(lib, h, n)
 
 
@@ -284,3 +287,29 @@ def query_directed(lab_out, lab_in, pairs, lib=None):
                                                       (lab_in.hub_pos, np.int32), (lab_in.dist, np.int64))]
     lib.oracle_query2(*(x.ctypes.data for x in a), pairs.ctypes.data, len(pairs), out.ctypes.data)
     return out
+
+
+def combined_directed(row_ptr, col, w, order):
+    """The combined graph of a directed graph: the graph on ids [0, n), its
+    reversal on [n, 2n), ranking interleaved (v at rank position 2 pos(v), its
+    reversed copy at 2 pos(v) + 1). Its labels on [0, n) are the in-labels,
+    on [n, 2n) the out-labels, each with hub position // 2."""
+    row_ptr, col, w, order = _graph_args(row_ptr, col, w, order)
+    n = len(row_ptr) - 1
+    trow, tcol, tw = _transpose(row_ptr, col, w)
+    row2 = np.concatenate([row_ptr, row_ptr[-1] + trow[1:]])
+    col2 = np.concatenate([col, tcol + n]).astype(np.int32)
+    w2 = np.concatenate([w, tw]).astype(np.int32)
+    order2 = np.empty(2 * n, dtype=np.int32)
+    order2[0::2] = order
+    order2[1::2] = order + n
+    return row2, col2, w2, order2
+
+
+def split_combined(lab, n):
+    """(L_out, L_in) from a labeling of the combined graph."""
+    off = lab.offsets
+    tin = int(off[n])
+    lin = Labels(off[:n + 1].copy(), lab.hub_pos[:tin] // 2, lab.dist[:tin])
+    lout = Labels(off[n:] - tin, lab.hub_pos[tin:] // 2, lab.dist[tin:])
+    return lout, lin

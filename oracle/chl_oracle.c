@@ -192,17 +192,26 @@ typedef struct {
     int64_t* off;      /* [n+1] */
     int32_t* hub;      /* rank positions */
     int64_t* dist;
+    int32_t half;      /* combined graph of a directed graph: n/2, else 0 */
 } prefix_t;
 
 /* Length of the shortest root-u walk through a hub of the prefix: the
  * minimum of d(h,x) + d(x,u) over prefix hubs x in both label sets
- * (INF64 if none). */
+ * (INF64 if none). On the combined graph of a directed graph (the graph on
+ * ids [0, half), its reversal on [half, 2 half), rank positions interleaved:
+ * v at 2 pos(v), its reversed copy at 2 pos(v) + 1), d(x,u) is u's label
+ * from x, and d(h,x) is the label of h's copy in the other half from x's
+ * copy, at rank position x ^ 1 (the footnote of Section 1 gives a directed
+ * graph forward and backward labels; the test itself is Section 4.3's). */
 static int64_t prefix_query(const prefix_t* P, int32_t h, int32_t u) {
-    int64_t i = P->off[h], ie = P->off[h + 1], j = P->off[u], je = P->off[u + 1];
+    const int32_t flip = P->half ? 1 : 0;
+    const int32_t hg = flip ? (h < P->half ? h + P->half : h - P->half) : h;
+    int64_t i = P->off[hg], ie = P->off[hg + 1], j = P->off[u], je = P->off[u + 1];
     int64_t best = INF64;
     while (i < ie && j < je) {
-        if (P->hub[i] < P->hub[j]) i++;
-        else if (P->hub[i] > P->hub[j]) j++;
+        const int32_t xh = P->hub[i] ^ flip;
+        if (xh < P->hub[j]) i++;
+        else if (xh > P->hub[j]) j++;
         else {
             int64_t s = P->dist[i] + P->dist[j];
             if (s < best) best = s;
@@ -455,7 +464,7 @@ static void prefix_free(prefix_t* P) { free(P->off); free(P->hub); free(P->dist)
 oracle_run* oracle_run_roots_levels(int32_t n, const int64_t* row_ptr, const int32_t* col,
                                     const int32_t* wt, const int32_t* order,
                                     const int32_t* roots, int64_t nroots,
-                                    const int32_t* bounds, int32_t nb, int32_t pmain,
+                                    const int32_t* bounds, int32_t nb, int32_t pmain, int32_t half,
                                     int nthreads) {
     int32_t gl = nb > 0 ? bounds[nb - 1] : 0;
     if (gl > n) gl = n;
@@ -475,6 +484,7 @@ oracle_run* oracle_run_roots_levels(int32_t n, const int64_t* row_ptr, const int
         prefix_t P;
         int pr = j > 0;
         if (pr) prefix_build(&P, n, lo, lv, ld, cnt);
+        P.half = half;
         oracle_run* R = run_roots_p(n, row_ptr, col, wt, order, lvl, hi - lo, 1, nthreads, pr ? &P : NULL);
         for (int32_t r = lo; r < hi; r++) {
             lv[r] = R->lv[r - lo]; ld[r] = R->ld[r - lo]; cnt[r] = R->cnt[r - lo]; hst[r] = R->stats[r - lo];
@@ -496,6 +506,7 @@ oracle_run* oracle_run_roots_levels(int32_t n, const int64_t* row_ptr, const int
     }
     prefix_t P;
     if (pmain > 0) prefix_build(&P, n, pmain, lv, ld, cnt);
+    P.half = half;
     oracle_run* L = run_roots_p(n, row_ptr, col, wt, order, late, nlate, 1, nthreads, pmain > 0 ? &P : NULL);
     oracle_run* R = (oracle_run*)calloc(1, sizeof(oracle_run));
     R->n = n; R->nroots = nroots;

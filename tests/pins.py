@@ -566,6 +566,26 @@ def check_symmetric_as_directed(lib, n, m, seed):
     assert oracle_labels(lo) == oracle_labels(lab) == oracle_labels(li)
 
 
+def check_directed_pruned(lib, n, m, wmax, seed):
+    """Rank-prefix pruning on the combined graph of a directed graph (the
+    graph and its reversal, ranks interleaved; d(h, x) from the out-labels,
+    d(x, u) from the in-labels of the prefix): both label sets equal the
+    definition on Floyd-Warshall distances, for several level schedules,
+    odd prefix sizes included."""
+    g = np.random.default_rng(seed)
+    a = [(int(x), int(y), int(z)) for x, y, z in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = csr_from_arcs(n, a)
+    order = gg.random_rank(n, seed)
+    D = floyd_warshall(n, row, col, w)
+    want_out, want_in = brute_labels(D, order), brute_labels(np.ascontiguousarray(D.T), order)
+    r2, c2, w2, o2 = oracle.combined_directed(row, col, w, order)
+    for lv, pm in (([2, 6, 18], 18), ([3, 7, 21], 21), ([4], 4)):
+        lab = oracle.chl_pruned(r2, c2, w2, o2, levels=lv, pmain=pm, half=n, threads=2, lib=lib)
+        lo, li = oracle.split_combined(lab, n)
+        assert oracle_labels(lo) == want_out and oracle_labels(li) == want_in, (lv, pm)
+
+
 def run_all(lib):
     """Every pin, smallish; used against planted mistakes."""
     check_golden(lib, "fig1_example.txt")
@@ -591,3 +611,5 @@ def run_all(lib):
         check_directed_bruteforce(lib, 20, 50, 1 + s % 3, 600 + s)
     check_directed_cycle(lib, 9, 3)
     check_symmetric_as_directed(lib, 25, 40, 7)
+    for s in range(3):
+        check_directed_pruned(lib, 24, 70, 1 + s, 800 + s)

@@ -241,3 +241,8 @@ def test_directed_rmat10_queries_match_dijkstra(lib):
         ref = oracle.sssp(c["row_ptr"], c["col"], c["w"], int(s), lib=lib)
         sel = pairs[:, 0] == s
         assert np.array_equal(q[sel], ref[pairs[sel, 1]])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_directed_pruned_levels(lib, seed):
+    pins.check_directed_pruned(lib, 20 + 3 * seed, 60 + 10 * seed, 1 + seed % 3, 900 + seed)

@@ -56,6 +56,8 @@ MUTANTS = {
                    "int64_t s = dist_out[i] + dist_in[j];\n                if (best < 0 || s > best) best = s;"),
     # directed query merge advances the wrong list
     "query2_skip": ("if (hub_out[i] < hub_in[j]) i++;", "if (hub_out[i] < hub_in[j]) j++;"),
+    # directed pruning: the root's own in-labels taken for d(h, x)
+    "dir_prune_side": ("const int32_t flip = P->half ? 1 : 0;", "const int32_t flip = 0;"),
     "sssp_w": ("int64_t nd = it.d + wt[e];\n            if (nd < out[col[e]])",
                "int64_t nd = it.d + wt[row_ptr[it.v]];\n            if (nd < out[col[e]])"),
 }
