@@ -332,6 +332,21 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
         chl_server_destroy(s);
         return CHL_ERR_HIP;
     }
+    // take the build budget from the driver now, in pieces, and hand it back
+    // to the pool, which keeps it (release threshold above): builds admitted
+    // later allocate from memory the pool already holds instead of mapping
+    // new memory while query batches run
+    if (!s->bs.empty()) {
+        const size_t piece = (size_t)256 << 20;
+        std::vector<void*> held;
+        for (size_t got = 0; got + piece <= so.mem_budget; got += piece) {
+            void* p = nullptr;
+            if (hipMallocAsync(&p, piece, s->bs[0]) != hipSuccess || !p) break;
+            held.push_back(p);
+        }
+        for (void* p : held) (void)hipFreeAsync(p, s->bs[0]);
+        (void)hipStreamSynchronize(s->bs[0]);
+    }
     *out = s;
     return CHL_OK;
 }
