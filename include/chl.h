@@ -336,6 +336,10 @@ typedef struct chl_server_opts {
 } chl_server_opts;
 
 void chl_server_opts_default(chl_server_opts* o);
+/* Builds allocate from the device's default stream-ordered memory pool; the
+ * server sets that pool to keep up to mem_budget bytes and takes them from
+ * the driver here (in 256 MB pieces, freed back to the pool), so that builds
+ * admitted later do not map new memory while query batches run. */
 int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_server** out);
 
 /* Register a resident labeling for queries; returns its graph id (>= 0) in
