@@ -153,11 +153,14 @@ def test_directed_in_server():
 
 
 @pytest.mark.parametrize("kw", [dict(prune_hubs=-1), dict(prune_hubs=64), dict(prune_hubs=255, team_wgs=3),
-                                dict(prune_hubs=1024, wg_size=128), dict(autotune=False)])
+                                dict(prune_hubs=1024, wg_size=128), dict(prune_hubs=1023, wg_size=128),
+                                dict(autotune=False)])
 def test_directed_pruning_invariance(kw):
     """Rank-prefix pruning across the two directions (d(h, x) from the
-    out-labels, d(x, u) from the in-labels; odd prefix sizes included): the
-    same label sets with every prefix and team size."""
+    out-labels, d(x, u) from the in-labels; odd prefix sizes included, with
+    teams and with wide levels only, whose roots start in the order of their
+    partners' prefix-label counts): the same label sets with every prefix
+    and team size."""
     c = gg.make_config("rmat12d9")
     _say("directed pruning", kw)
     L, _, _, _ = _check(c["row_ptr"], c["col"], c["w"], c["order"], c["pairs"][:5000], str(kw), **kw)
