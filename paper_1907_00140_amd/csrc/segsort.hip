@@ -1,12 +1,16 @@
 // Segmented ascending sort of 64-bit keys: every segment [off[i], off[i+1])
 // is sorted on its own. Three tiers by segment length:
-//   <= 64      one wave per segment, bitonic network across the lanes;
-//   <= LCAP    one block per segment, bitonic network in LDS;
+//   <= 256     one wave per segment, bitonic network in registers: 1, 2 or 4
+//              keys per lane, position e * 64 + lane for the lane's key e;
+//              partners 64 or more positions apart sit in the same lane,
+//              closer ones are exchanged with lane shuffles;
+//   <= LCAP    one 1024-thread block per segment, bitonic network in LDS;
 //   larger     one block per segment, bitonic network in global memory.
-// The LDS and global tiers use the form of the bitonic network in which every
-// comparator moves the smaller key to the lower index (the first step of each
-// merge compares mirrored positions), so a length that is not a power of two
-// is handled as if padded with all-ones keys that never move into range.
+// A length that is not a power of two is padded with all-ones keys, which
+// sort to the end and are not stored. The LDS and global tiers use the form
+// of the network in which every comparator moves the smaller key to the lower
+// index (the first step of each merge compares mirrored positions), so their
+// padding is virtual.
 #include "internal.h"
 
 namespace chl {
@@ -15,6 +19,49 @@ namespace {
 
 constexpr int LCAP = 8192;
 constexpr int BLK = 256;
+constexpr int BLKL = 1024;
+
+template <int E>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E], int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j >= 1; j >>= 1) {
+            if (j >= 64) {
+                const int je = j >> 6;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    if (e & je) continue;
+                    const bool up = ((e * 64 + lane) & k) == 0;
+                    const uint64_t a = x[e], b = x[e | je];
+                    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    x[e] = up ? lo : hi;
+                    x[e | je] = up ? hi : lo;
+                }
+            } else {
+                const bool lower = (lane & j) == 0;
+#pragma unroll
+                for (int e = 0; e < E; e++) {
+                    const uint64_t y = __shfl_xor(x[e], j);
+                    const bool up = ((e * 64 + lane) & k) == 0;
+                    const uint64_t mn = x[e] < y ? x[e] : y, mx = x[e] < y ? y : x[e];
+                    x[e] = (up == lower) ? mn : mx;
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ void wave_sort(uint64_t* __restrict__ a, int len, int lane) {
+    uint64_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; e++) x[e] = e * 64 + lane < len ? a[e * 64 + lane] : ~0ull;
+    wave_bitonic<E>(x, lane);
+#pragma unroll
+    for (int e = 0; e < E; e++)
+        if (e * 64 + lane < len) a[e * 64 + lane] = x[e];
+}
 
 __global__ __launch_bounds__(BLK) void k_sort_wave(uint64_t* __restrict__ keys,
                                                    const int64_t* __restrict__ off, int64_t nseg) {
@@ -24,18 +71,10 @@ __global__ __launch_bounds__(BLK) void k_sort_wave(uint64_t* __restrict__ keys,
     for (int64_t s = wave; s < nseg; s += nwaves) {
         const int64_t b = off[s];
         const int len = (int)(off[s + 1] - b);
-        if (len <= 1 || len > 64) continue;
-        uint64_t x = lane < len ? keys[b + lane] : ~0ull;
-        for (int k = 2; k <= 64; k <<= 1) {
-            for (int j = k >> 1; j >= 1; j >>= 1) {
-                uint64_t y = __shfl_xor(x, j);
-                bool up = (lane & k) == 0;            // ascending half
-                bool lower = (lane & j) == 0;
-                uint64_t mn = x < y ? x : y, mx = x < y ? y : x;
-                x = (up == lower) ? mn : mx;
-            }
-        }
-        if (lane < len) keys[b + lane] = x;
+        if (len <= 1 || len > 256) continue;
+        if (len <= 64) wave_sort<1>(keys + b, len, lane);
+        else if (len <= 128) wave_sort<2>(keys + b, len, lane);
+        else wave_sort<4>(keys + b, len, lane);
     }
 }
 
@@ -44,34 +83,36 @@ __device__ __forceinline__ void cas(uint64_t* a, int i, int j) {
     if (y < x) { a[i] = y; a[j] = x; }
 }
 
-__global__ __launch_bounds__(BLK) void k_sort_lds(uint64_t* __restrict__ keys,
-                                                  const int64_t* __restrict__ off, int64_t nseg) {
+__global__ __launch_bounds__(BLKL) void k_sort_lds(uint64_t* __restrict__ keys,
+                                                   const int64_t* __restrict__ off, int64_t nseg) {
     __shared__ uint64_t a[LCAP];
     for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
         const int64_t b = off[s];
         const int len = (int)(off[s + 1] - b);
-        if (len <= 64 || len > LCAP) continue;
-        int p2 = 128;
-        while (p2 < len) p2 <<= 1;
-        for (int i = threadIdx.x; i < p2; i += BLK) a[i] = i < len ? keys[b + i] : ~0ull;
+        if (len <= 256 || len > LCAP) continue;
+        int lp = 9;
+        while ((1 << lp) < len) lp++;
+        const int p2 = 1 << lp;
+        for (int i = threadIdx.x; i < p2; i += BLKL) a[i] = i < len ? keys[b + i] : ~0ull;
         __syncthreads();
-        for (int k = 2; k <= p2; k <<= 1) {
+        for (int lk = 1; lk <= lp; lk++) {
+            const int k = 1 << lk;
             // mirrored step: pairs (i, i ^ (k - 1)) inside blocks of k
-            for (int t = threadIdx.x; t < p2 / 2; t += BLK) {
-                int i = (t / (k >> 1)) * k + (t % (k >> 1));
-                int j = i ^ (k - 1);
-                cas(a, i, j);
+            for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
+                const int i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
+                cas(a, i, i ^ (k - 1));
             }
             __syncthreads();
-            for (int j = k >> 2; j >= 1; j >>= 1) {
-                for (int t = threadIdx.x; t < p2 / 2; t += BLK) {
-                    int i = (t / j) * 2 * j + (t % j);
+            for (int lj = lk - 2; lj >= 0; lj--) {
+                const int j = 1 << lj;
+                for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
+                    const int i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
                     cas(a, i, i + j);
                 }
                 __syncthreads();
             }
         }
-        for (int i = threadIdx.x; i < len; i += BLK) keys[b + i] = a[i];
+        for (int i = threadIdx.x; i < len; i += BLKL) keys[b + i] = a[i];
         __syncthreads();
     }
 }
@@ -83,12 +124,14 @@ __global__ __launch_bounds__(BLK) void k_sort_global(uint64_t* __restrict__ keys
         const int64_t len = off[s + 1] - b;
         if (len <= LCAP) continue;
         uint64_t* a = keys + b;
-        int64_t p2 = 1;
-        while (p2 < len) p2 <<= 1;
-        for (int64_t k = 2; k <= p2; k <<= 1) {
-            for (int64_t t = threadIdx.x; t < p2 / 2; t += BLK) {
-                int64_t i = (t / (k >> 1)) * k + (t % (k >> 1));
-                int64_t j = i ^ (k - 1);
+        int lp = 0;
+        while (((int64_t)1 << lp) < len) lp++;
+        const int64_t half = (int64_t)1 << (lp - 1);
+        for (int lk = 1; lk <= lp; lk++) {
+            const int64_t k = (int64_t)1 << lk;
+            for (int64_t t = threadIdx.x; t < half; t += BLK) {
+                const int64_t i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
+                const int64_t j = i ^ (k - 1);
                 if (j < len) {                          // j >= len holds a virtual all-ones key
                     uint64_t x = a[i], y = a[j];
                     if (y < x) { a[i] = y; a[j] = x; }
@@ -96,9 +139,10 @@ __global__ __launch_bounds__(BLK) void k_sort_global(uint64_t* __restrict__ keys
             }
             __threadfence_block();
             __syncthreads();
-            for (int64_t j = k >> 2; j >= 1; j >>= 1) {
-                for (int64_t t = threadIdx.x; t < p2 / 2; t += BLK) {
-                    int64_t i = (t / j) * 2 * j + (t % j);
+            for (int lj = lk - 2; lj >= 0; lj--) {
+                const int64_t j = (int64_t)1 << lj;
+                for (int64_t t = threadIdx.x; t < half; t += BLK) {
+                    const int64_t i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
                     if (i + j < len) {
                         uint64_t x = a[i], y = a[i + j];
                         if (y < x) { a[i] = y; a[i + j] = x; }
@@ -124,7 +168,7 @@ int launch_segsort_u64(uint64_t* keys, const int64_t* off, int64_t nseg, int64_t
                        hipStream_t st) {
     if (nseg <= 0 || total <= 1) return 0;
     hipLaunchKernelGGL(k_sort_wave, dim3(grid_cap((nseg + 3) / 4)), dim3(BLK), 0, st, keys, off, nseg);
-    hipLaunchKernelGGL(k_sort_lds, dim3(grid_cap(nseg < 8192 ? nseg : 8192)), dim3(BLK), 0, st, keys, off, nseg);
+    hipLaunchKernelGGL(k_sort_lds, dim3(grid_cap(nseg < 2048 ? nseg : 2048)), dim3(BLKL), 0, st, keys, off, nseg);
     hipLaunchKernelGGL(k_sort_global, dim3(grid_cap(nseg < 1024 ? nseg : 1024)), dim3(BLK), 0, st, keys, off, nseg);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

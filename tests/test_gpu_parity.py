@@ -388,3 +388,29 @@ def test_query_long_lists_complete_graph():
     pairs = np.concatenate([pairs, np.stack([g.integers(0, n, 5000), g.integers(0, n, 5000)], 1).astype(np.int32)])
     q = L.query(pairs).cpu().numpy()
     assert np.array_equal(q, (pairs[:, 0] != pairs[:, 1]).astype(np.int64))
+
+
+def test_sort_tiers_two_hubs():
+    """Rows and label lists of every length tier of the segmented sort: two
+    hubs adjacent to 9000 leaves (rows of 9000 arcs; the hub ranked last
+    holds 9003 labels) and vertices of degree 63 to 4097 around the 64-, 128-,
+    256- and 8192-key tier bounds; labels bit-exact, queries equal the
+    oracle's."""
+    g = np.random.default_rng(7)
+    nl = 9000
+    degs = [63, 64, 65, 100, 128, 129, 200, 255, 256, 257, 1000, 4097]
+    n = 2 + nl + len(degs)
+    leaves = np.arange(2, 2 + nl)
+    e = [(0, int(v), 1) for v in leaves] + [(1, int(v), 1) for v in leaves]
+    for i, d in enumerate(degs):
+        for u, w in zip(g.choice(leaves, d, replace=False), g.integers(1, 4, d)):
+            e.append((2 + nl + i, int(u), int(w)))
+    row, col, w = pins.csr_from_edges(n, e)
+    order = np.concatenate([[0], g.permutation(np.arange(2, n)), [1]]).astype(np.int32)
+    _say("sort tiers", n, len(col))
+    ref = oracle.chl(row, col, w, order)
+    assert np.diff(ref.offsets).max() > 8192 and np.diff(row).max() > 8192
+    L, off, hub, dist = gpu_labels(row, col, w, order)
+    assert_same_labels(off, hub, dist, ref)
+    pairs = np.stack([g.integers(0, n, 20000), g.integers(0, n, 20000)], 1).astype(np.int32)
+    assert np.array_equal(L.query(pairs).cpu().numpy(), oracle.query(ref, pairs))
