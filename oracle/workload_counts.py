@@ -36,16 +36,19 @@ LEVEL0 = 16
 LEVEL_LABELS_X2 = 1 << 21
 
 
-def level_bounds(labels_per_root, gmax):
+def level_bounds(labels_per_root, gmax, first=None):
     """The pruning-level schedule of the batched build: roots [0, 16) first;
     after a level whose roots have at least 2^21 labels in total the next
-    level is twice as large a prefix, else eight times, up to gmax. Labels
-    per root do not depend on the schedule, so any run's counts fix it."""
+    level is twice as large a prefix, else eight times, up to gmax; `first`,
+    when given, is the factor of the first pruned level instead (4 for a
+    directed build's combined graph). Labels per root do not depend on the
+    schedule, so any run's counts fix it."""
     g = min(LEVEL0, gmax)
     lv = [g]
     lab = int(labels_per_root[0:g].sum())
     while g < gmax:
-        g2 = min(gmax, (2 if lab >= LEVEL_LABELS_X2 else 8) * g)
+        f = first if first and g == LEVEL0 else (2 if lab >= LEVEL_LABELS_X2 else 8)
+        g2 = min(gmax, f * g)
         lab = int(labels_per_root[g:g2].sum())
         lv.append(g2)
         g = g2
@@ -74,7 +77,7 @@ def counts_directed(name, threads=None):
     lv = [g for g in LEVELS if g < gmax] + [gmax]
     t = time.time()
     p = oracle.chl_pruned(r2, c2, w2, o2, levels=lv, pmain=lv[-1], half=n, threads=threads)
-    lv2 = level_bounds(p.stats[:, 2], gmax)
+    lv2 = level_bounds(p.stats[:, 2], gmax, first=4)
     if lv2 != lv:
         lv = lv2
         p = oracle.chl_pruned(r2, c2, w2, o2, levels=lv, pmain=lv[-1], half=n, threads=threads)
@@ -110,7 +113,7 @@ def counts(name, threads=None, pruned_only=False, levels=True):
     if lv and levels:
         t = time.time()
         p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1], threads=threads)
-        lv2 = level_bounds(p.stats[:, 2], gmax)
+        lv2 = level_bounds(p.stats[:, 2], gmax, first=4)
         if lv2 != lv:
             lv = lv2
             p = oracle.chl_pruned(c["row_ptr"], c["col"], c["w"], c["order"], levels=lv, pmain=lv[-1],

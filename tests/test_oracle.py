@@ -177,6 +177,8 @@ def test_level_schedule_rule():
     assert level_bounds(lab, 4096) == [16, 32, 256, 2048, 4096]
     assert level_bounds(np.zeros(100, np.int64), 50) == [16, 50]
     assert level_bounds(np.zeros(100, np.int64), 8) == [8]
+    # a directed build's first pruned level grows by 4
+    assert level_bounds(np.zeros(4096, np.int64), 2048, first=4) == [16, 64, 512, 2048]
 
 
 @pytest.mark.parametrize("seed", range(8))
