@@ -278,15 +278,19 @@ struct TeamCfg {
 };
 
 // Run the batched kernel (or the team kernel when team is set) over roots
-// (NULL = all, in rank order) until every root has emitted, growing the pool
-// when it fills up.
+// (NULL = all, in rank order; roots_in_place: the list is already in B.roots
+// on the stream) until every root has emitted, growing the pool when it
+// fills up.
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
                 const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
-                int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr) {
+                int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr,
+                bool roots_in_place = false) {
     std::vector<int32_t> pending;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
         HIPCHK(hipMemcpyAsync(B.roots, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, st));
+        dev_roots = B.roots;
+    } else if (roots_in_place) {
         dev_roots = B.roots;
     }
     for (;;) {
@@ -334,6 +338,11 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         rest.insert(rest.end(), failed.begin(), failed.end());
         if (roots_host) {
             rest.insert(rest.end(), roots_host + next, roots_host + nroots);
+        } else if (dev_roots) {
+            std::vector<int32_t> tail((size_t)(nroots - next));
+            if (!tail.empty())
+                HIPCHK(hipMemcpy(tail.data(), B.roots + next, tail.size() * 4, hipMemcpyDeviceToHost));
+            rest.insert(rest.end(), tail.begin(), tail.end());
         } else {
             for (int32_t r = next; r < nroots; r++) rest.push_back(root_base + r);
         }
@@ -398,18 +407,27 @@ int run_plain(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int ear
     return 0;
 }
 
-uint64_t graph_signature(const chl_graph* g, const int32_t* order, int64_t* dev_tmp, hipStream_t st) {
-    // a few row offsets, arcs and ranking entries sampled at fixed positions
+// A signature of the input: a few row offsets, arcs and ranking entries
+// sampled at fixed positions. sample_graph queues the sample and its
+// read-back on the stream; graph_signature mixes it once the stream has been
+// synchronised.
+int sample_graph(const chl_graph* g, const int32_t* order, int64_t* dev_tmp, hipStream_t st) {
+    HostCtl* hc = host_ctl();
+    if (!hc) return CHL_ERR_HIP;
+    std::memset(hc->smp, 0, sizeof(hc->smp));
+    if (launch_sample_input(g->n, g->n_arcs, g->row_ptr, g->col, g->w, order, dev_tmp, st) ||
+        hipMemcpyAsync(hc->smp, dev_tmp, sizeof(hc->smp), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return CHL_ERR_HIP;
+    return CHL_OK;
+}
+
+uint64_t graph_signature(const chl_graph* g) {
     uint64_t h = 1469598103934665603ull;
     auto mix = [&](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
     mix((uint64_t)g->n);
     mix((uint64_t)g->n_arcs);
     HostCtl* hc = host_ctl();
     if (!hc) return h;
-    std::memset(hc->smp, 0, sizeof(hc->smp));
-    if (launch_sample_input(g->n, g->n_arcs, g->row_ptr, g->col, g->w, order, dev_tmp, st) == 0 &&
-        hipMemcpyAsync(hc->smp, dev_tmp, sizeof(hc->smp), hipMemcpyDeviceToHost, st) == hipSuccess)
-        (void)hipStreamSynchronize(st);
     for (int i = 0; i < 64; i++) mix((uint64_t)hc->smp[i]);
     return h;
 }
@@ -648,6 +666,9 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     }
     int32_t* tfar2 = tmax ? A.get<int32_t>((size_t)tmax * n) : nullptr;
     long long* tstate = tmax ? A.get<long long>((size_t)tmax * TEAM_WORDS) : nullptr;
+    // sort keys and segment bounds of a wide level's root order
+    uint64_t* lkeys = A.get<uint64_t>((size_t)std::max<int32_t>(1, gmax));
+    int64_t* loff = A.get<int64_t>(2);
     if (A.oom) return CHL_ERR_OOM;
     auto team_for = [&](int32_t nr, TeamCfg& tc) -> const TeamCfg* {
         if (!team_shape(nr, tc) || tc.nteams > tmax) return nullptr;
@@ -722,30 +743,17 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             const TeamCfg* tcp = team_for(g2 - g, tc);
             // a level of more trees than slots runs them in waves, and a large
             // tree that starts late sets the level's end: start the trees
-            // whose roots carry the most prefix labels first, a cheap
-            // predictor of a large pruned tree (R-MAT 16, level [128, 1024):
-            // rank correlation 0.45 with the tree's duration; builds 4.5%
-            // faster, the directed R-MAT 16 build 5%)
-            std::vector<int32_t> lroots;
-            if (!tcp) {
-                std::vector<int64_t> po((size_t)(g2 - g) + 1);
-                HIPCHK(hipMemcpyAsync(po.data(), B.poff + g, po.size() * 8, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                lroots.resize((size_t)(g2 - g));
-                for (int32_t i = 0; i < g2 - g; i++) lroots[(size_t)i] = g + i;
-                // a directed build prunes root h with the prefix labels of
-                // its partner h ^ 1 (TreeParams::partner), which is outside
-                // [g, g2) only at an odd end of the range
-                auto size = [&](int32_t h) {
-                    const int32_t hp = h ^ B.partner;
-                    const size_t i = (size_t)((hp >= g && hp < g2 ? hp : h) - g);
-                    return po[i + 1] - po[i];
-                };
-                std::stable_sort(lroots.begin(), lroots.end(),
-                                 [&](int32_t x, int32_t y) { return size(x) > size(y); });
-            }
-            if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, lroots.empty() ? nullptr : lroots.data(), g2 - g,
-                                    st, &launches, 2, g, tcp))
+            // whose roots carry the most prefix labels first (a directed
+            // build counts those of the partner h ^ 1, whose labels prune
+            // h's tree), a cheap predictor of a large pruned tree (R-MAT 16,
+            // level [128, 1024): rank correlation 0.45 with the tree's
+            // duration; builds 4.5% faster, the directed R-MAT 16 build 5%).
+            // The order is computed and sorted on the stream, into B.roots.
+            const bool ordered = !tcp;
+            if (ordered && launch_level_order(B.poff, g, g2, B.partner, lkeys, loff, B.roots, st))
+                return CHL_ERR_HIP;
+            if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g, tcp,
+                                    ordered))
                 return r;
             if (int r = regroup()) return r;
             level_labels = B.cursor_base - before;
@@ -832,23 +840,18 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (launch_segsort_u64(rarc, rrow, n, B.m, nullptr, st)) return CHL_ERR_HIP;
     if (!directed && launch_check_symmetric(n, B.m, rrow, rarc, err, st)) return CHL_ERR_HIP;
     HIPCHK(hipMemcpyAsync(hub_order, order, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+    // the tuner caches' input signature is sampled here (the input is valid),
+    // so that its read-back completes with the symmetry check's
+    int64_t* smp = A.get<int64_t>(64);
+    if (!smp) return CHL_ERR_OOM;
+    if (int r = sample_graph(g, order, smp, st)) return r;
     HIPCHK(hipMemcpyAsync(hc0->c32, err, 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (hc0->c32[0]) return CHL_ERR_INVALID_ARG;
-    A.drop(rdeg);
-    A.drop(cnt);
-    S.prep_ms = tprep.stop();
-    B.g = RGraph{n, B.m, rrow, rarc};
-    {
-        int64_t* smp = A.get<int64_t>(64);
-        if (!smp) return CHL_ERR_OOM;
-        B.sig = graph_signature(g, order, smp, st);
-        A.drop(smp);
-    }
+    tprep.record_end();
     // 32-bit keys are exact when no simple path can reach 2^31 - 1
     B.key_bits = ((double)(n - 1) * (double)B.maxw <= 2147483646.0) ? 32 : 64;
     S.key_bits = B.key_bits;
 
+    // the build's buffers are taken while the renumbering runs
     B.failed = A.get<int32_t>(n);
     B.roots = A.get<int32_t>(n);
     B.far2 = A.get<int32_t>(n);
@@ -862,6 +865,14 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     B.pool.cursor = B.ctl64 + 0;
     B.pool.fail_base = B.ctl64 + 1;
     if (A.oom) return CHL_ERR_OOM;
+    HIPCHK(hipStreamSynchronize(st));
+    if (hc0->c32[0]) return CHL_ERR_INVALID_ARG;
+    S.prep_ms = tprep.elapsed();
+    B.sig = graph_signature(g);
+    A.drop(smp);
+    A.drop(rdeg);
+    A.drop(cnt);
+    B.g = RGraph{n, B.m, rrow, rarc};
     if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
 
     // ---- rank-prefix pruning (Section 4.3) in levels: the trees of roots

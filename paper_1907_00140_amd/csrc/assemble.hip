@@ -123,6 +123,39 @@ __global__ void k_move_groups(int32_t n, const int64_t* __restrict__ off_old, co
     }
 }
 
+// sort key of root h of a level: (2^32 - 1 - its prefix-label count) << 32 | h
+__global__ void k_level_keys(const int64_t* __restrict__ poff, int32_t g, int32_t g2, int32_t partner,
+                             uint64_t* __restrict__ keys, int64_t* __restrict__ off2) {
+    const int32_t nr = g2 - g;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x) {
+        const int32_t h = g + i;
+        int32_t hp = h ^ partner;
+        if (hp < g || hp >= g2) hp = h;
+        const uint32_t size = (uint32_t)(poff[hp + 1] - poff[hp]);
+        keys[i] = ((uint64_t)(0xFFFFFFFFu - size) << 32) | (uint32_t)h;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        off2[0] = 0;
+        off2[1] = nr;
+    }
+}
+
+__global__ void k_level_roots(const uint64_t* __restrict__ keys, int32_t nr, int32_t* __restrict__ roots) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += gridDim.x * blockDim.x)
+        roots[i] = (int32_t)(uint32_t)keys[i];
+}
+
+int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partner, uint64_t* keys,
+                       int64_t* off2, int32_t* roots, hipStream_t st) {
+    const int32_t nr = g2 - g;
+    if (nr <= 0) return 0;
+    const int blocks = (nr + 255) / 256 < 1024 ? (nr + 255) / 256 : 1024;
+    hipLaunchKernelGGL(k_level_keys, dim3(blocks), dim3(256), 0, st, poff, g, g2, partner, keys, off2);
+    if (launch_segsort_u64(keys, off2, 1, nr, nullptr, st)) return -1;
+    hipLaunchKernelGGL(k_level_roots, dim3(blocks), dim3(256), 0, st, keys, nr, roots);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
                          const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
                          int32_t* fill, void* scan_temp, hipStream_t st) {

@@ -169,6 +169,12 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
 int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
                          const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
                          int32_t* fill, void* scan_temp, hipStream_t st);
+// assemble.hip: the roots [g, g2) of a pruning level into roots[0, g2 - g),
+// most prefix labels first (poff: the prefix groups; a directed build counts
+// the group of the partner h ^ 1 when it lies in [g, g2)), ties by rank; keys
+// holds g2 - g words and off2 two. Everything stays on the stream.
+int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partner, uint64_t* keys,
+                       int64_t* off2, int32_t* roots, hipStream_t st);
 // assemble.hip: totals of the per-root statistics (settled, arcs, stopped
 // early) into sums[0..2] (zeroed by the caller)
 int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);

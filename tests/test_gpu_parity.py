@@ -115,10 +115,13 @@ def test_team_sizes_rmat14(team):
 
 def test_team_grid():
     """Teams on a grid (unpruned first level only when the probe drops the
-    pruning) give the oracle's labels."""
+    pruning) give the oracle's labels; so do pruning levels without teams
+    (256-thread workgroups), whose reordered roots fill the label pool and
+    resume."""
     c = gg.make_config("grid128x128_5")
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
-    for kw in (dict(team_wgs=4), dict(team_wgs=16, prune_hubs=256, autotune=False)):
+    for kw in (dict(team_wgs=4), dict(team_wgs=16, prune_hubs=256, autotune=False),
+               dict(prune_hubs=1024, wg_size=256, autotune=False)):
         _say("team grid", kw)
         L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], **kw)
         assert_same_labels(off, hub, dist, ref)
