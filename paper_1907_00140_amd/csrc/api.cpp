@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -893,11 +894,15 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         auto it = g_prune_keep.find(TuneKey{n, B.m, B.maxw, -1, B.sig});
         known_unpruned = it != g_prune_keep.end() && !it->second;
     }
+    // (the levels' end is only recorded: the main phase's set-up is queued
+    // behind their last kernels, and the time is read after a later
+    // synchronisation)
+    std::unique_ptr<Timer> tp;
     if (o.mode == CHL_MODE_BATCHED && o.prune_hubs >= 0 && n >= 64 && !known_unpruned) {
-        Timer tp(st);
+        tp.reset(new Timer(st));
         if (int r = run_levels(A, B, o, scan_tmp, st, launches, grown)) return r;
         prefix_launches = launches;
-        prune_ms = tp.stop();
+        tp->record_end();
     }
 
     // ---- parameters
@@ -922,7 +927,6 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     Slots s{};
     if (int r = alloc_slots(A, B, o.mode == CHL_MODE_PLAIN ? 1 : k, s, st)) return r;
     HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
     Timer ttree(st);
     std::vector<int32_t> sel;
     if (o.root_count > 0)
@@ -934,6 +938,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
                               sel.empty() ? grown : 0);
     if (r) return r;
     S.tree_ms = ttree.stop();
+    if (tp) prune_ms = tp->elapsed();
     S.prefix_ms = prune_ms;
     S.kernel_ms = B.kernel_ms;
     S.kernel_launches = B.kernel_launches;
