@@ -245,7 +245,7 @@ def make_config(name):
     rmat<s>_<i> : serving build requests, R-MAT scale s, seed 500+i,
                   weights [1,1000], degree rank.
     Smaller stand-ins used by tests: grid<r>x<c>_<seed>, rmat<s>s<seed>,
-    rmat<s>d<seed> (directed).
+    rmat<s>d<seed> (directed), rmat<s>s<seed>w<b> (weights [1, 2^b]).
     """
     if name == "rmat16dir" or (name.startswith("rmat") and name[4:].replace("d", "", 1).isdigit() and "d" in name[4:]):
         if name == "rmat16dir":
@@ -275,6 +275,12 @@ def make_config(name):
         s, i = int(s), int(i)
         n, u, v, w = rmat_edges(s, 8, *RMAT_ABC, 500 + i, 1, 1000)
         seed, qseed, q = 500 + i, 600 + i, 10_000
+    elif name.startswith("rmat") and "s" in name[4:] and "w" in name[4:]:
+        s, rest = name[4:].split("s")
+        sd, wb = rest.split("w")
+        s, sd, wb = int(s), int(sd), int(wb)
+        n, u, v, w = rmat_edges(s, 8, *RMAT_ABC, sd, 1, 1 << wb)
+        seed, qseed, q = sd, sd + 100, 10_000
     elif name.startswith("rmat") and "s" in name[4:]:
         s, sd = name[4:].split("s")
         s, sd = int(s), int(sd)

@@ -268,6 +268,7 @@ int chl_query_paths(const chl_labels* h, const int32_t* parent, const int32_t* s
                     void* stream);
 
 /* ---- statistics ---- */
+#define CHL_MAX_LEVELS 16
 typedef struct chl_stats {
     int64_t n;               /* vertices (= roots) */
     int64_t labels;          /* total labels */
@@ -294,6 +295,15 @@ typedef struct chl_stats {
     double assemble_ms;      /* device time of label assembly */
     double prep_ms;          /* validation + rank renumbering */
     double tune_ms;          /* autotuner probe time (0 when cached or off) */
+    /* rank-prefix levels grown before the main phase (Section 4.3): level i
+       holds the roots [level_end[i-1], level_end[i]) (level_end[-1] = 0) and
+       is pruned by the labels of the hubs [0, level_end[i-1]) (level 0 is
+       unpruned); the main phase grows the roots [level_end[levels-1], n)
+       pruned by the hubs [0, prune_hubs). levels = 0: no level ran. */
+    int64_t levels;
+    int64_t level_end[CHL_MAX_LEVELS];
+    double level_ms[CHL_MAX_LEVELS];   /* device time of each level's tree launches */
+    int64_t level_teams[CHL_MAX_LEVELS];  /* workgroups per tree of the level (1: batched kernel) */
 } chl_stats;
 
 /* Totals into *totals (host, may be NULL). per_root (may be NULL) receives
@@ -336,17 +346,34 @@ typedef struct chl_server_opts {
 } chl_server_opts;
 
 void chl_server_opts_default(chl_server_opts* o);
-/* Builds allocate from the device's default stream-ordered memory pool; the
- * server sets that pool to keep up to mem_budget bytes and takes them from
- * the driver here (in 256 MB pieces, freed back to the pool), so that builds
- * admitted later do not map new memory while query batches run. */
+/* Create a server. alloc == NULL: builds allocate from the device's default
+ * stream-ordered memory pool on their build streams; the server sets that
+ * pool to keep up to mem_budget bytes and takes them from the driver here
+ * (in 256 MB pieces, freed back to the pool), so that builds admitted later
+ * do not map new memory while query batches run. alloc != NULL: builds (and
+ * the labelings they produce, released by chl_server_destroy) take device
+ * memory from that allocator instead; it must be callable from the server's
+ * threads and stay valid until chl_server_destroy returns (the server
+ * synchronises a build's stream before it returns memory to it, since such
+ * an allocator is not ordered with the build streams).
+ * Budget: a build is admitted when its footprint estimate
+ * (chl_server_build_footprint) fits what other builds hold; memory it needs
+ * beyond the estimate is charged while it runs, and an allocation that would
+ * take the builds past mem_budget fails, after which the request is queued
+ * again with a larger estimate (at most four attempts; then its status is
+ * CHL_ERR_OOM). Builds in flight never hold more than mem_budget bytes
+ * together; a finished build's labeling stays resident outside the budget,
+ * like the labelings added with chl_server_add_labels. */
 int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_server** out);
 
 /* Register a resident labeling for queries; returns its graph id (>= 0) in
  * *graph_id. The server does not take ownership. */
 int chl_server_add_labels(chl_server* s, const chl_labels* h, int32_t* graph_id);
 
-/* Schedule q queries against graph_id: host arrays pairs[2q] (input ids) and
+/* Requests are submitted before chl_server_start (or after chl_server_wait
+ * has returned); a submit while the server runs returns CHL_ERR_BUSY.
+ *
+ * Schedule q queries against graph_id: host arrays pairs[2q] (input ids) and
  * t_arrival[q] (non-decreasing seconds). Results go to host out[q] (int64)
  * and per-query latency to host lat[q] (seconds); both must stay valid until
  * chl_server_wait returns. */
@@ -363,8 +390,13 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
                             double t_arrival, int32_t* graph_id, double* lat, int32_t* status);
 
 /* Device-memory footprint (bytes) that admission charges for a build of a
- * graph with n vertices and n_arcs arcs on this server. */
+ * graph with n vertices and n_arcs arcs on this server (an estimate; see
+ * chl_server_create for what happens when a build needs more). */
 size_t chl_server_build_footprint(const chl_server* s, int32_t n, int64_t n_arcs);
+
+/* Largest number of device-memory bytes charged to builds at one time since
+ * the server was created (never more than mem_budget). */
+size_t chl_server_budget_peak(const chl_server* s);
 
 /* Start the clock and the dispatch thread; returns immediately. */
 int chl_server_start(chl_server* s);

@@ -159,6 +159,28 @@ def chl_pruned(row_ptr, col, w, order, eta=None, grown=None, levels=None, pmain=
     return _assemble(lib, h, n)
 
 
+def chl_pruned_roots(row_ptr, col, w, order, root_pos, levels, pmain, threads=None, lib=None, half=0):
+    """Work statistics [len(root_pos), 4] = (settled, arcs, labels, early) of
+    the pruned trees of the given roots (rank positions) under the level
+    schedule of chl_pruned; only the levels up to the largest requested root
+    and the requested later roots are grown."""
+    lib = lib or load()
+    row_ptr, col, w, order = _graph_args(row_ptr, col, w, order)
+    n = len(row_ptr) - 1
+    lv = np.ascontiguousarray(levels, dtype=np.int32)
+    rp = np.ascontiguousarray(root_pos, dtype=np.int32)
+    threads = threads or min(16, os.cpu_count() or 1)
+    h = lib.oracle_run_roots_levels(n, row_ptr.ctypes.data, col.ctypes.data, w.ctypes.data,
+                                    order.ctypes.data, rp.ctypes.data, len(rp), lv.ctypes.data, len(lv),
+                                    int(pmain), int(half), threads)
+    try:
+        stats = np.zeros((len(rp), 4), dtype=np.int64)
+        lib.oracle_run_stats(h, stats.ctypes.data)
+    finally:
+        lib.oracle_run_free(h)
+    return stats
+
+
 def roots(row_ptr, col, w, order, root_pos, mode=MODE_PLANT, threads=None, lib=None):
     """Labels of selected roots (given by rank position). Returns a list of
     (vertices int32, dists int64) sorted by vertex, one per root, and stats

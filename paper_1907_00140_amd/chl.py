@@ -57,7 +57,9 @@ class CStats(C.Structure):
         "n", "labels", "settled", "arcs", "early_trees", "key_bits", "roots_in_flight",
         "wg_size", "delta", "prune_hubs", "prefix_roots", "launches", "clock_khz")] + [(f, C.c_double) for f in (
             "tree_ms", "prefix_ms", "kernel_ms")] + [("kernel_launches", C.c_int64)] + [
-        (f, C.c_double) for f in ("assemble_ms", "prep_ms", "tune_ms")]
+        (f, C.c_double) for f in ("assemble_ms", "prep_ms", "tune_ms")] + [
+        ("levels", C.c_int64), ("level_end", C.c_int64 * 16), ("level_ms", C.c_double * 16),
+        ("level_teams", C.c_int64 * 16)]
 
 
 class CServerOpts(C.Structure):
@@ -103,6 +105,7 @@ def load(path=LIB_PATH):
             "chl_server_submit_queries": (C.c_int, [vp, i32, vp, vp, i64, vp, vp]),
             "chl_server_submit_build": (C.c_int, [vp, i32, i64, vp, vp, vp, vp, C.c_double, vp, vp, vp]),
             "chl_server_build_footprint": (C.c_size_t, [vp, i32, i64]),
+            "chl_server_budget_peak": (C.c_size_t, [vp]),
             "chl_server_start": (C.c_int, [vp]),
             "chl_server_wait": (C.c_int, [vp]),
             "chl_server_labels": (vp, [vp, i32]),
@@ -130,12 +133,18 @@ class TorchAllocator:
     """chl_allocator backed by torch's caching allocator (device memory and
     its accounting stay with torch)."""
 
-    def __init__(self, device=None):
+    def __init__(self, device=None, cap=None):
+        """cap: refuse (return NULL for) an allocation that would take the
+        live bytes past `cap` (None: no limit)."""
         self.device = torch.device(device or "cuda")
         self._live = {}
         self._mu = threading.Lock()
+        self.calls = 0          # number of allocations made through this allocator
+        self.cap = cap
 
         def _alloc(nbytes, ctx):
+            if self.cap is not None and self.live_bytes() + int(nbytes) > self.cap:
+                return None
             try:
                 t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
             except RuntimeError:
@@ -143,6 +152,7 @@ class TorchAllocator:
             p = t.data_ptr()
             with self._mu:
                 self._live[p] = t
+                self.calls += 1
             return p
 
         def _free(ptr, ctx):
@@ -247,11 +257,20 @@ class Labels:
                "chl_labels_export")
         return off
 
-    def hub_vertex(self):
+    def hub_vertex(self, device="cpu", stream=None):
+        """Input id of the vertex at each hub rank position (int32[n]), as a
+        host tensor or, with device="cuda", a device tensor."""
         n, _ = self.info()
-        out = np.zeros(n, np.int32)
-        _check(self.lib.chl_labels_hub_vertex(self._h, out.ctypes.data, 1, _stream_ptr()), "chl_labels_hub_vertex")
-        return torch.from_numpy(out)
+        if device == "cpu":
+            out = np.zeros(n, np.int32)
+            _check(self.lib.chl_labels_hub_vertex(self._h, out.ctypes.data, 1, _stream_ptr(stream)),
+                   "chl_labels_hub_vertex")
+            return torch.from_numpy(out)
+        out = torch.empty(n, dtype=torch.int32, device=device)
+        _check(self.lib.chl_labels_hub_vertex(self._h, out.data_ptr(), 0, _stream_ptr(stream)),
+               "chl_labels_hub_vertex")
+        (stream or torch.cuda.current_stream()).synchronize()
+        return out
 
     def query(self, pairs, out=None, stream=None):
         """Distances for pairs [q, 2] (input ids) as an int64 device tensor."""
@@ -314,6 +333,9 @@ class Labels:
             ptr = pr.ctypes.data
         _check(self.lib.chl_build_stats(self._h, C.byref(s), ptr, 1, _stream_ptr()), "chl_build_stats")
         d = {f: getattr(s, f) for f, _ in CStats._fields_}
+        nl = int(s.levels)
+        for f in ("level_end", "level_ms", "level_teams"):
+            d[f] = list(d[f])[:nl]
         if per_root:
             d["per_root"] = pr
         return d
@@ -358,7 +380,7 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
         o.root_begin, o.root_count, o.root_stride = (int(x) for x in roots)
     o.prune_hubs = int(prune_hubs)
     o.team_wgs = int(team_wgs)
-    al = default_allocator() if allocator == "torch" else None
+    al = allocator if isinstance(allocator, TorchAllocator) else default_allocator() if allocator == "torch" else None
     out = C.c_void_p()
     f = lib.chl_build_directed if directed else lib.chl_build
     code = f(C.byref(g), od.data_ptr(), C.byref(o), C.byref(al.c) if al else None, _stream_ptr(stream),

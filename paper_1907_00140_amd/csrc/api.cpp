@@ -187,6 +187,14 @@ struct Build {
     int64_t kernel_launches = 0;
     uint64_t sig = 0;                    // graph and ranking signature (tuning caches)
     unsigned long long last_used = 0;    // pool cursor after the last tree launch
+    // the rank-prefix levels as grown (chl_stats::levels ...)
+    int nlev = 0;
+    int64_t lv_end[CHL_MAX_LEVELS] = {};
+    double lv_ms[CHL_MAX_LEVELS] = {};
+    int64_t lv_team[CHL_MAX_LEVELS] = {};
+    void record_level(int32_t end, double ms, int team) {
+        if (nlev < CHL_MAX_LEVELS) { lv_end[nlev] = end; lv_ms[nlev] = ms; lv_team[nlev] = team; nlev++; }
+    }
 };
 
 // labels emitted by a pruning level above which the next level is only
@@ -678,9 +686,11 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
         return &tc;
     };
     TeamCfg tc0;
-    if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0,
-                            team_for(g, tc0)))
+    const TeamCfg* tcp0 = team_for(g, tc0);
+    double ms0 = B.kernel_ms;
+    if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0, tcp0))
         return r;
+    B.record_level(g, B.kernel_ms - ms0, tcp0 ? tcp0->size : 1);
     if (int r = regroup()) return r;
     unsigned long long level_labels = B.cursor_base;
     grown = g;
@@ -753,9 +763,11 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             const bool ordered = !tcp;
             if (ordered && launch_level_order(B.poff, g, g2, B.partner, lkeys, loff, B.roots, st))
                 return CHL_ERR_HIP;
+            const double ms1 = B.kernel_ms;
             if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g, tcp,
                                     ordered))
                 return r;
+            B.record_level(g2, B.kernel_ms - ms1, tcp ? tcp->size : 1);
             if (int r = regroup()) return r;
             level_labels = B.cursor_base - before;
             g = g2;
@@ -942,6 +954,13 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     S.prefix_ms = prune_ms;
     S.kernel_ms = B.kernel_ms;
     S.kernel_launches = B.kernel_launches;
+    // a root-subset build discards the levels' labels (run_levels)
+    S.levels = o.root_count > 0 ? 0 : B.nlev;
+    for (int i = 0; i < B.nlev; i++) {
+        S.level_end[i] = B.lv_end[i];
+        S.level_ms[i] = B.lv_ms[i];
+        S.level_teams[i] = B.lv_team[i];
+    }
     S.launches = launches - prefix_launches;
     free_slots(A, s);
     HostCtl* hc = host_ctl();

@@ -43,27 +43,74 @@ struct BuildReq {
     double* lat;
     int32_t* status;
     size_t footprint;
+    int attempts = 0;
     bool started = false, done = false;
 };
 
-// Stream-ordered device allocator of one build stream, with byte accounting.
+void bump_peak(std::atomic<int64_t>& peak, int64_t v) {
+    int64_t p = peak.load();
+    while (v > p && !peak.compare_exchange_weak(p, v)) {
+    }
+}
+
+// Device allocator of one build stream, with byte accounting against the
+// server's budget. A build is admitted with an estimate of its footprint
+// (charged); an allocation that takes its live bytes past the charge first
+// charges the difference to the shared budget and fails (the build then
+// returns CHL_ERR_OOM and is queued again with a larger estimate) when that
+// would overrun mem_budget. Memory comes from the stream-ordered pool of the
+// build stream, or from the caller's allocator when the server was created
+// with one.
 struct StreamAlloc {
     hipStream_t s;
-    std::atomic<int64_t> bytes{0};
+    std::atomic<int64_t>* budget_used = nullptr;   // the server's charged bytes
+    std::atomic<int64_t>* budget_peak = nullptr;
+    int64_t budget = 0;                            // mem_budget
+    const chl_allocator* user = nullptr;           // the caller's allocator or NULL
     std::mutex mu;
+    int64_t bytes = 0;      // live bytes of the current build
+    int64_t charged = 0;    // bytes charged to the budget for the current build
+    int64_t peak = 0;       // largest live bytes of the current build
+    bool refused = false;   // an allocation was refused for the budget
     std::vector<std::pair<void*, size_t>> live;
+    void start(int64_t reserve) {
+        std::lock_guard<std::mutex> lk(mu);
+        bytes = 0; charged = reserve; peak = 0; refused = false;
+    }
     static void* alloc(size_t b, void* ctx) {
         auto* a = (StreamAlloc*)ctx;
+        {
+            std::lock_guard<std::mutex> lk(a->mu);
+            const int64_t need = a->bytes + (int64_t)b - a->charged;
+            if (need > 0) {
+                int64_t cur = a->budget_used->load();
+                do {
+                    if (cur + need > a->budget) { a->refused = true; return nullptr; }
+                } while (!a->budget_used->compare_exchange_weak(cur, cur + need));
+                a->charged += need;
+                bump_peak(*a->budget_peak, cur + need);
+            }
+            a->bytes += (int64_t)b;
+            a->peak = std::max(a->peak, a->bytes);
+        }
         void* p = nullptr;
-        if (hipMallocAsync(&p, b, a->s) != hipSuccess) return nullptr;
+        if (a->user) p = a->user->alloc(b, a->user->ctx);
+        else if (hipMallocAsync(&p, b, a->s) != hipSuccess) p = nullptr;
         std::lock_guard<std::mutex> lk(a->mu);
+        if (!p) { a->bytes -= (int64_t)b; return nullptr; }
         a->live.push_back({p, b});
-        a->bytes += (int64_t)b;
         return p;
     }
     static void release(void* p, void* ctx) {
         auto* a = (StreamAlloc*)ctx;
-        (void)hipFreeAsync(p, a->s);
+        if (a->user) {
+            // a caller's allocator is not ordered with the build stream: the
+            // work queued there may still use the memory
+            (void)hipStreamSynchronize(a->s);
+            a->user->free(p, a->user->ctx);
+        } else {
+            (void)hipFreeAsync(p, a->s);
+        }
         std::lock_guard<std::mutex> lk(a->mu);
         for (size_t i = 0; i < a->live.size(); i++)
             if (a->live[i].first == p) {
@@ -71,6 +118,19 @@ struct StreamAlloc {
                 a->live.erase(a->live.begin() + i);
                 break;
             }
+        // (memory of finished builds' labelings is not in `live`: it no
+        // longer counts against the current build)
+    }
+    // the build is over: its charge returns to the budget (the budget covers
+    // builds in flight; a finished labeling is resident like the ones added
+    // with chl_server_add_labels)
+    int64_t finish() {
+        std::lock_guard<std::mutex> lk(mu);
+        const int64_t ret = charged;
+        charged = 0;
+        live.clear();
+        bytes = 0;
+        return ret;
     }
 };
 
@@ -89,6 +149,7 @@ struct Batch {
 
 struct chl_server {
     chl_server_opts o{};
+    chl_allocator user{};        // the caller's allocator (user.alloc == NULL: stream-ordered pools)
     hipStream_t qs{};
     std::vector<hipStream_t> bs;
     std::vector<std::unique_ptr<StreamAlloc>> ba;
@@ -104,6 +165,7 @@ struct chl_server {
     std::vector<std::thread> workers;
     std::atomic<bool> running{false};
     std::atomic<int64_t> budget_used{0};
+    std::atomic<int64_t> budget_peak{0};     // largest budget_used seen
     std::atomic<int32_t> builds_left{0};
     int64_t queries_left = 0;
     clk::time_point t0;
@@ -118,7 +180,9 @@ struct chl_server {
 namespace {
 
 size_t build_footprint(int32_t n, int64_t m, int k) {
-    // CSR copy + renumbered CSR + per-tree slots + a label pool of 64 per vertex
+    // CSR copy + renumbered CSR + per-tree slots + a label pool of 64 per
+    // vertex. An estimate: a build that needs more charges the rest while it
+    // runs (StreamAlloc), or is queued again with a larger estimate.
     size_t slots = (size_t)k * ((size_t)n * 24 + (size_t)n / 2);
     return (size_t)m * 24 + (size_t)n * 64 + slots + (size_t)n * 64 * 28;
 }
@@ -129,6 +193,7 @@ void chl_server::run_build(size_t idx, int slot) {
     BuildReq& b = builds[idx];
     hipStream_t s = bs[slot];
     StreamAlloc* a = ba[slot].get();
+    a->start((int64_t)b.footprint);
     chl_allocator al{StreamAlloc::alloc, StreamAlloc::release, a};
     int code = CHL_OK;
     int64_t* d_row = nullptr;
@@ -163,7 +228,18 @@ void chl_server::run_build(size_t idx, int slot) {
         if (p) StreamAlloc::release(p, a);
     (void)hipStreamSynchronize(s);
     double tc = now();
+    const bool refused = code == CHL_ERR_OOM && a->refused;
+    const int64_t peak = a->peak;
+    budget_used -= a->finish();
     std::lock_guard<std::mutex> lk(mu);
+    bs_busy[slot] = false;
+    if (refused && b.attempts < 4) {
+        // the estimate was too small and other builds held the rest of the
+        // budget: queue the request again, charged with what it reached
+        b.footprint = std::max<size_t>(2 * (size_t)peak, 2 * b.footprint);
+        b.started = false;
+        return;
+    }
     *b.status = code;
     *b.lat = tc - b.t;
     if (code == CHL_OK) {
@@ -174,8 +250,6 @@ void chl_server::run_build(size_t idx, int slot) {
         *b.gid_out = -1;
     }
     b.done = true;
-    budget_used -= (int64_t)b.footprint;
-    bs_busy[slot] = false;
     builds_left--;
 }
 
@@ -219,7 +293,8 @@ void chl_server::dispatch_loop() {
                 if (slot < 0) break;                                                  // wait for a stream
                 bs_busy[slot] = true;
                 b.started = true;
-                budget_used += (int64_t)b.footprint;
+                b.attempts++;
+                bump_peak(budget_peak, budget_used += (int64_t)b.footprint);
                 workers.emplace_back(&chl_server::run_build, this, i, slot);
                 idle = false;
             }
@@ -286,8 +361,8 @@ void chl_server_opts_default(chl_server_opts* o) {
 }
 
 int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_server** out) {
-    (void)alloc;  // builds use stream-ordered allocations on their own streams
     if (!out) return CHL_ERR_INVALID_ARG;
+    if (alloc && (!alloc->alloc || !alloc->free)) return CHL_ERR_INVALID_ARG;
     chl_server_opts so;
     chl_server_opts_default(&so);
     if (o) so = *o;
@@ -295,6 +370,7 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
         return CHL_ERR_INVALID_ARG;
     auto* s = new chl_server();
     s->o = so;
+    if (alloc) s->user = *alloc;
     // builds allocate from the device's default stream-ordered pool: let it
     // keep up to the build budget instead of returning memory to the driver
     // at every synchronisation (a fresh driver allocation can stall the
@@ -315,6 +391,10 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
         s->bs.push_back(st);
         auto a = std::make_unique<StreamAlloc>();
         a->s = st;
+        a->budget_used = &s->budget_used;
+        a->budget_peak = &s->budget_peak;
+        a->budget = (int64_t)so.mem_budget;
+        a->user = s->user.alloc ? &s->user : nullptr;
         s->ba.push_back(std::move(a));
         s->bs_busy.push_back(false);
     }
@@ -336,7 +416,7 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
     // to the pool, which keeps it (release threshold above): builds admitted
     // later allocate from memory the pool already holds instead of mapping
     // new memory while query batches run
-    if (!s->bs.empty()) {
+    if (!s->bs.empty() && !s->user.alloc) {
         const size_t piece = (size_t)256 << 20;
         std::vector<void*> held;
         for (size_t got = 0; got + piece <= so.mem_budget; got += piece) {
@@ -362,8 +442,8 @@ int chl_server_add_labels(chl_server* s, const chl_labels* h, int32_t* graph_id)
 int chl_server_submit_queries(chl_server* s, int32_t graph_id, const int32_t* pairs, const double* t_arrival,
                               int64_t q, int64_t* out, double* lat) {
     if (!s || q < 0 || (q && (!pairs || !t_arrival || !out || !lat))) return CHL_ERR_INVALID_ARG;
-    if (s->running) return CHL_ERR_BUSY;
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->running) return CHL_ERR_BUSY;   // the dispatcher reads the request lists without the lock
     if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) return CHL_ERR_INVALID_ARG;
     for (int64_t i = 1; i < q; i++)
         if (t_arrival[i] < t_arrival[i - 1]) return CHL_ERR_INVALID_ARG;
@@ -380,7 +460,6 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
                             int32_t* graph_id, double* lat, int32_t* status) {
     if (!s || n < 1 || n_arcs < 0 || !row_ptr || !order || !graph_id || !lat || !status) return CHL_ERR_INVALID_ARG;
     if (n_arcs && (!col || !w)) return CHL_ERR_INVALID_ARG;
-    if (s->running) return CHL_ERR_BUSY;
     BuildReq b;
     b.n = n; b.m = n_arcs;
     b.row.assign(row_ptr, row_ptr + n + 1);
@@ -390,6 +469,7 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
     b.t = t_arrival; b.gid_out = graph_id; b.lat = lat; b.status = status;
     b.footprint = build_footprint(n, n_arcs, s->o.build_wg);
     std::lock_guard<std::mutex> lk(s->mu);
+    if (s->running) return CHL_ERR_BUSY;
     // keep builds in arrival order
     auto it = std::upper_bound(s->builds.begin(), s->builds.end(), t_arrival,
                                [](double t, const BuildReq& r) { return t < r.t; });
@@ -398,13 +478,19 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
     return CHL_OK;
 }
 
+size_t chl_server_budget_peak(const chl_server* s) {
+    return s ? (size_t)s->budget_peak.load() : 0;
+}
+
 size_t chl_server_build_footprint(const chl_server* s, int32_t n, int64_t n_arcs) {
     if (!s || n < 1 || n_arcs < 0) return 0;
     return build_footprint(n, n_arcs, s->o.build_wg);
 }
 
 int chl_server_start(chl_server* s) {
-    if (!s || s->running) return CHL_ERR_INVALID_ARG;
+    if (!s) return CHL_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->running) return CHL_ERR_INVALID_ARG;
     s->running = true;
     s->all_done = false;
     s->t0 = clk::now();

@@ -26,8 +26,11 @@ class QueryTicket:
 
 
 class Server:
-    def __init__(self, mem_budget=16 << 30, max_batch=1 << 16, build_streams=2, build_wg=128):
+    def __init__(self, mem_budget=16 << 30, max_batch=1 << 16, build_streams=2, build_wg=128, allocator=None):
+        """allocator: a chl.TorchAllocator for the builds' device memory (None:
+        the stream-ordered pools of the build streams)."""
         self.lib = load()
+        self._alloc = allocator
         o = CServerOpts()
         self.lib.chl_server_opts_default(C.byref(o))
         o.mem_budget = int(mem_budget)
@@ -35,7 +38,8 @@ class Server:
         o.build_streams = int(build_streams)
         o.build_wg = int(build_wg)
         h = C.c_void_p()
-        _check(self.lib.chl_server_create(C.byref(o), None, C.byref(h)), "chl_server_create")
+        _check(self.lib.chl_server_create(C.byref(o), C.byref(allocator.c) if allocator is not None else None,
+                                          C.byref(h)), "chl_server_create")
         self._h = h
         self._keep = []
 
@@ -72,6 +76,9 @@ class Server:
 
     def footprint(self, n, n_arcs) -> int:
         return int(self.lib.chl_server_build_footprint(self._h, int(n), int(n_arcs)))
+
+    def budget_peak(self) -> int:
+        return int(self.lib.chl_server_budget_peak(self._h))
 
     def start(self):
         _check(self.lib.chl_server_start(self._h), "chl_server_start")

@@ -83,3 +83,50 @@ def test_admission_by_footprint():
         off, hub, dist = srv.labels(tk.gid.value).export("cpu")
         assert_same_labels(off.numpy(), hub.numpy(), dist.numpy(), ref)
     srv.close()
+
+
+def test_allocator_honoured():
+    """A server created with an allocator takes every build's device memory
+    from it and returns all of it when destroyed."""
+    from paper_1907_00140_amd import chl, serve
+    al = chl.TorchAllocator()
+    cfgs = [gg.make_config("rmat%d_%d" % (10 + i, i)) for i in range(3)]
+    srv = serve.Server(mem_budget=4 << 30, build_streams=2, build_wg=64, allocator=al)
+    tks = [srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.001 * i) for i, c in enumerate(cfgs)]
+    srv.start()
+    srv.wait()
+    assert al.calls > 0
+    for c, tk in zip(cfgs, tks):
+        assert tk.status.value == 0
+        off, hub, dist = srv.labels(tk.gid.value).export("cpu")
+        ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+        assert_same_labels(off.numpy(), hub.numpy(), dist.numpy(), ref, "built with the caller's allocator")
+    srv.close()
+    assert al.live_bytes() == 0, "the server kept memory of the caller's allocator"
+
+
+def test_budget_never_overrun():
+    """Builds whose labels outgrow the admission estimate (a grid: hundreds of
+    labels per vertex) charge the rest while they run; two of them together
+    need more than the budget, so one is queued again and runs after the
+    other. Both complete, equal to the same build alone, and the builds in
+    flight never held more than the budget."""
+    from paper_1907_00140_amd import chl, serve
+    c = gg.make_config("grid256x256_3")
+    alone = [x.numpy() for x in chl.build(c["row_ptr"], c["col"], c["w"], c["order"]).export("cpu")]
+    probe = serve.Server(mem_budget=1 << 20, build_streams=2, build_wg=64)
+    est = probe.footprint(c["n"], len(c["col"]))
+    probe.close()
+    budget = 3 * est
+    srv = serve.Server(mem_budget=budget, build_streams=2, build_wg=64)
+    tks = [srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.0) for _ in range(2)]
+    srv.start()
+    srv.wait()
+    _say("estimate %d MB, budget %d MB, peak charged %d MB, latencies %s" % (
+        est >> 20, budget >> 20, srv.budget_peak() >> 20, [round(t.lat.value, 4) for t in tks]))
+    assert srv.budget_peak() <= budget
+    for tk in tks:
+        assert tk.status.value == 0, tk.status.value
+        got = [x.numpy() for x in srv.labels(tk.gid.value).export("cpu")]
+        assert all(np.array_equal(x, y) for x, y in zip(got, alone))
+    srv.close()

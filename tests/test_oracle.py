@@ -170,7 +170,13 @@ def test_level_schedule_rule():
     """The pruning-level schedule the work counts use: roots [0, 16) first,
     then a prefix 2x larger after a level whose roots emitted >= 2^21 labels,
     else 8x larger, capped at the prefix size."""
-    from oracle.workload_counts import level_bounds
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "make_workload_counts", os.path.join(os.path.dirname(__file__), "golden", "make_workload_counts.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    level_bounds = mod.level_bounds
     lab = np.zeros(70_000, np.int64)
     lab[:16] = 200_000          # 3.2 M labels: work-bound level -> x2
     lab[16:32] = 100_000        # 1.6 M labels -> x8
