@@ -257,6 +257,21 @@ int chl_query_path_hops(const chl_labels* h, const int32_t* parent, const int32_
                         const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
                         void* stream);
 
+/* The variant of chl_query_path_hops for callers that cannot allocate device
+ * memory during the call (code under stream capture, tight serving loops,
+ * hosts that forbid allocation): the same arguments, results and errors, but
+ * the per-pair vertex counts and the prefix sum's temporaries live in a
+ * fixed device array of the library (8 * CHL_NOALLOC_MAX_PAIRS + 64 KiB
+ * bytes, one copy per GPU, held until the process ends) instead of memory
+ * taken from the labeling's allocator. q > CHL_NOALLOC_MAX_PAIRS gives
+ * CHL_ERR_INVALID_ARG. Calls on one GPU share that array: the library
+ * serialises them (each synchronises `stream` before it returns), so calls
+ * from several host threads take turns. */
+#define CHL_NOALLOC_MAX_PAIRS (1 << 20)
+int chl_query_path_hops_noalloc(const chl_labels* h, const int32_t* parent, const int32_t* slot,
+                                const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
+                                void* stream);
+
 /* Write the paths: the vertices (input ids, u first, v last) of pair k go
  * to path[path_off[k] .. path_off[k+1]-1] (device int32, caller-owned,
  * path_off[q] entries) for path_off as returned by chl_query_path_hops for

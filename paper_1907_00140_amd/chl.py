@@ -24,6 +24,7 @@ ERRORS = {
     -4: "CHL_ERR_DIST_OVERFLOW", -5: "CHL_ERR_NO_DEVICE", -6: "CHL_ERR_BUSY",
 }
 MODE_BATCHED, MODE_PLAIN = 0, 1
+NOALLOC_MAX_PAIRS = 1 << 20     # CHL_NOALLOC_MAX_PAIRS
 
 
 class ChlError(RuntimeError):
@@ -97,6 +98,7 @@ def load(path=LIB_PATH):
             "chl_microbench_atomic_min": (C.c_int, [vp, i64, C.c_int, i64, vp, vp, vp]),
             "chl_query_path_hops": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "chl_query_paths": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
+            "chl_query_path_hops_noalloc": (C.c_int, [vp, vp, vp, vp, i64, vp, vp, vp]),
             "chl_build_stats": (C.c_int, [vp, vp, vp, C.c_int, vp]),
             "chl_labels_free": (None, [vp]),
             "chl_server_opts_default": (None, [vp]),
@@ -299,16 +301,22 @@ class Labels:
                                            _stream_ptr(stream)), "chl_labels_parents")
         return par[:total], slot[:total]
 
-    def path_hops(self, pairs, parent, slot, stream=None):
-        """(hops int64[q], path_off int64[q+1]) device tensors for pairs [q, 2]."""
+    def path_hops(self, pairs, parent, slot, stream=None, noalloc=False, out=None):
+        """(hops int64[q], path_off int64[q+1]) device tensors for pairs [q, 2].
+        noalloc=True calls chl_query_path_hops_noalloc (no device memory taken
+        from the labeling's allocator; q <= NOALLOC_MAX_PAIRS); out = (hops,
+        path_off) caller tensors to fill."""
         p = _dev(pairs, torch.int32).reshape(-1, 2)
         q = p.shape[0]
-        hops = torch.empty(max(q, 1), dtype=torch.int64, device="cuda")
-        off = torch.empty(q + 1, dtype=torch.int64, device="cuda")
-        _check(self.lib.chl_query_path_hops(self._h, parent.data_ptr(), slot.data_ptr(), p.data_ptr(), q,
-                                            hops.data_ptr(), off.data_ptr(), _stream_ptr(stream)),
-               "chl_query_path_hops")
-        return hops[:q], off
+        if out is None:
+            hops = torch.empty(max(q, 1), dtype=torch.int64, device="cuda")
+            off = torch.empty(q + 1, dtype=torch.int64, device="cuda")
+        else:
+            hops, off = out
+        f = self.lib.chl_query_path_hops_noalloc if noalloc else self.lib.chl_query_path_hops
+        _check(f(self._h, parent.data_ptr(), slot.data_ptr(), p.data_ptr(), q, hops.data_ptr(), off.data_ptr(),
+                 _stream_ptr(stream)), "chl_query_path_hops_noalloc" if noalloc else "chl_query_path_hops")
+        return hops[:q], off[:q + 1]
 
     def paths(self, pairs, parent, slot, stream=None):
         """Shortest paths for pairs [q, 2]: (hops int64[q], path_off

@@ -40,6 +40,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <mutex>
 
 namespace chl {
 
@@ -382,6 +383,60 @@ extern "C" int chl_query_path_hops(const chl_labels* h, const int32_t* parent, c
         h->alloc.free(temp, h->alloc.ctx);
     }
     return rc;
+}
+
+// ---- the variant of chl_query_path_hops that allocates nothing: its
+// scratch (per-pair vertex counts and the scan's temporaries) is a
+// file-scope device array, one copy per GPU, whose address each device
+// reports once through hipGetSymbolAddress.
+namespace {
+constexpr size_t NOALLOC_BYTES = (size_t)CHL_NOALLOC_MAX_PAIRS * 8 + (64u << 10);
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;                       // one call at a time (the calls share the array)
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device address of this device's copy of the array (nullptr on failure)
+void* noalloc_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_noalloc_ptr[dev] = p;
+    }
+    return g_noalloc_ptr[dev];
+}
+}  // namespace
+
+extern "C" int chl_query_path_hops_noalloc(const chl_labels* h, const int32_t* parent, const int32_t* slot,
+                                           const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
+                                           void* stream) {
+    if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !hops || !parent || !slot))) return CHL_ERR_INVALID_ARG;
+    if (q > CHL_NOALLOC_MAX_PAIRS) return CHL_ERR_INVALID_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    if (q == 0) {
+        if (path_off && hipMemsetAsync(path_off, 0, 8, st) != hipSuccess) return CHL_ERR_HIP;
+        return CHL_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    unsigned char* base = (unsigned char*)noalloc_scratch();
+    if (!base) return CHL_ERR_HIP;
+    int64_t* len = nullptr;
+    void* temp = nullptr;
+    if (path_off) {
+        len = (int64_t*)base;                           // q entries, all written by the kernel
+        temp = base + (size_t)CHL_NOALLOC_MAX_PAIRS * 8;  // the scan's temporaries
+        if (scan_temp_bytes(q) > NOALLOC_BYTES - (size_t)CHL_NOALLOC_MAX_PAIRS * 8) return CHL_ERR_INVALID_ARG;
+    }
+    // with_err synchronises the stream before it returns, so the next call
+    // (serialised by the lock) never finds this call's work in flight
+    return with_err(h, st, [&]() {
+        if (launch_path<false>(h, parent, slot, pairs, q, hops, len, nullptr, nullptr, st)) return CHL_ERR_HIP;
+        if (len && launch_scan_i64(len, path_off, q, temp, st)) return CHL_ERR_HIP;
+        return CHL_OK;
+    });
 }
 
 extern "C" int chl_query_paths(const chl_labels* h, const int32_t* parent, const int32_t* slot,
