@@ -52,6 +52,10 @@ NAMES = {
 }
 
 
+def wname(name, m):
+    return NAMES[name] % m if "%d" in NAMES[name] else NAMES[name]
+
+
 def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -101,7 +105,7 @@ def timed_builds(chl, d, reps, stream, **kw):
         L = chl.build(*d, stream=stream, **kw)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
-    st = L.stats(per_root=True)
+    st = L.stats(per_root=not kw.get("directed", False))
     return float(np.median(times)), times, st, L
 
 
@@ -279,7 +283,7 @@ def workload(chl, gg, counts, name, dev, stream, reps, plain=None):
     b, runs, st, L = timed_builds(chl, d, reps, stream)
     qps, _ = queries_per_s(L, pairs, stream)
     units = method_units(counts, name, st)
-    r = {"workload": NAMES[name] % c["m"] if "%d" in NAMES[name] else NAMES[name], "n": c["n"], "edges": c["m"],
+    r = {"workload": wname(name, c["m"]), "n": c["n"], "edges": c["m"],
          "build_s": round(b, 4), "build_s_runs": [round(t, 4) for t in runs], "labels": int(st["labels"]),
          "queries": int(pairs.shape[0]), "queries_per_s": round(qps, 1), "schedule": schedule_key(st),
          "key_bits": int(st["key_bits"]), "roots_in_flight": st["roots_in_flight"], "wg_size": st["wg_size"],
@@ -364,6 +368,24 @@ def serve_full(chl, gg, stream, resident, reps=2):
             lat = np.concatenate([tk.lat for tk in tks])
             tend = max(float(np.max(tk.t + tk.lat)) for tk in tks)
             blat = np.array([b.lat.value for b in btk])
+            tr = srv.trace()
+            qb, bb = tr[tr[:, 0] == 0], tr[tr[:, 0] == 1]
+            dev_ms = (qb[:, 3] - qb[:, 2]) * 1e3
+            wait_ms = (qb[:, 2] - qb[:, 1]) * 1e3
+            slow = dev_ms > 1.0
+            # a slow batch overlapped a build when some build ran (admitted,
+            # not yet complete) while the batch was on the device
+            ov = np.array([bool(((bb[:, 2] < b[3]) & (bb[:, 3] > b[2])).any()) for b in qb[slow]]) \
+                if slow.any() and len(bb) else np.zeros(int(slow.sum()), bool)
+            anatomy = {"batches": int(len(qb)),
+                       "device_ms": {"p50": round(float(np.percentile(dev_ms, 50)), 3),
+                                     "p99": round(float(np.percentile(dev_ms, 99)), 3),
+                                     "max": round(float(dev_ms.max()), 3)},
+                       "dispatch_wait_ms": {"p50": round(float(np.percentile(wait_ms, 50)), 3),
+                                            "p99": round(float(np.percentile(wait_ms, 99)), 3),
+                                            "max": round(float(wait_ms.max()), 3)},
+                       "batches_over_1ms_on_device": int(slow.sum()),
+                       "of_which_during_a_build": int(ov.sum())}
             row["runs"].append({"achieved_qps": round(len(lat) / tend, 1),
                                 "p50_us": round(float(np.percentile(lat, 50)) * 1e6, 2),
                                 "p99_us": round(float(np.percentile(lat, 99)) * 1e6, 2),
@@ -371,6 +393,7 @@ def serve_full(chl, gg, stream, resident, reps=2):
                                 "per_graph_p99_us": [round(float(np.percentile(tk.lat, 99)) * 1e6, 2) for tk in tks],
                                 "build_latency_s": {"p50": round(float(np.median(blat)), 4),
                                                     "max": round(float(blat.max()), 4)},
+                                "batch_anatomy": anatomy,
                                 "wall_s": round(wall, 3)})
             srv.close()
             say("serving:", f, json.dumps(row["runs"][-1]))
@@ -517,6 +540,7 @@ def cpu_baseline(gg, counts, qout_c2=None, c2=None):
 
 
 def main():
+    global WORKLOAD
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -526,6 +550,8 @@ def main():
     ap.add_argument("--plain-full", default="",
                     help="workload whose plain one-root-per-launch form is measured outright (e.g. rmat16; takes "
                          "minutes); the others are estimated from root samples")
+    ap.add_argument("--headline", default=WORKLOAD, choices=sorted(NAMES),
+                    help="workload of the timed steps (default: R-MAT scale 20; others for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -550,6 +576,7 @@ def main():
         del x, y
     counts = json.load(open(COUNTS))
     stream = torch.cuda.current_stream()
+    WORKLOAD = args.headline
 
     say("headline: %s, %d warmup + %d steps" % (WORKLOAD, args.warmup, args.steps))
     H = headline(chl, gg, counts, args, dev, stream)
@@ -601,7 +628,7 @@ def main():
         L.free()
     directed = directed_measure(chl, gg, counts, stream) if "directed" in sec else None
     cpu = cpu_baseline(gg, counts, qout_c2, c2 if c2 is not None else gg.make_config("rmat16")) \
-        if "cpu" in sec else None
+        if "cpu" in sec and WORKLOAD == "rmat20" else None
 
     p50 = p99 = None
     if serving is not None:
@@ -613,7 +640,7 @@ def main():
         "value": line["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": line["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64" if line["key_bits"] == 64 else "u32", "data": "synthetic",
-        "config": {"workload": NAMES[WORKLOAD] % H["c"]["m"] + "; complete canonical labeling (chl_build, "
+        "config": {"workload": wname(WORKLOAD, H["c"]["m"]) + "; complete canonical labeling (chl_build, "
                                "batched form, rank-prefix pruning) + 10^6 uniform queries per step",
                    "mode": "batched", "schedule": line["schedule"],
                    "roots_in_flight": H["st"]["roots_in_flight"], "wg_size": H["st"]["wg_size"],

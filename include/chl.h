@@ -409,6 +409,17 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
  * chl_server_create for what happens when a build needs more). */
 size_t chl_server_build_footprint(const chl_server* s, int32_t n, int64_t n_arcs);
 
+/* Trace of the last run (since chl_server_start), for latency analysis: up
+ * to cap rows of 5 doubles (host memory) in completion order; *count
+ * receives the number of rows recorded (which may exceed cap).
+ *   query batch: (0, earliest scheduled arrival of its queries, time it was
+ *                 queued on the device, time its completion was observed,
+ *                 number of queries)
+ *   build:       (1, scheduled arrival, time it was admitted, time it
+ *                 completed, vertices)
+ * Times are seconds on the server's clock. */
+int chl_server_trace(chl_server* s, double* rows, int64_t cap, int64_t* count);
+
 /* Largest number of device-memory bytes charged to builds at one time since
  * the server was created (never more than mem_budget). */
 size_t chl_server_budget_peak(const chl_server* s);

@@ -108,6 +108,7 @@ def load(path=LIB_PATH):
             "chl_server_submit_build": (C.c_int, [vp, i32, i64, vp, vp, vp, vp, C.c_double, vp, vp, vp]),
             "chl_server_build_footprint": (C.c_size_t, [vp, i32, i64]),
             "chl_server_budget_peak": (C.c_size_t, [vp]),
+            "chl_server_trace": (C.c_int, [vp, vp, i64, vp]),
             "chl_server_start": (C.c_int, [vp]),
             "chl_server_wait": (C.c_int, [vp]),
             "chl_server_labels": (vp, [vp, i32]),
@@ -145,17 +146,19 @@ class TorchAllocator:
         self.cap = cap
 
         def _alloc(nbytes, ctx):
-            if self.cap is not None and self.live_bytes() + int(nbytes) > self.cap:
-                return None
+            # (an exception must not escape a ctypes callback: its return
+            # value would then be undefined)
             try:
+                if self.cap is not None and self.live_bytes + int(nbytes) > self.cap:
+                    return None
                 t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-            except RuntimeError:
+                p = t.data_ptr()
+                with self._mu:
+                    self._live[p] = t
+                    self.calls += 1
+                return p
+            except Exception:
                 return None
-            p = t.data_ptr()
-            with self._mu:
-                self._live[p] = t
-                self.calls += 1
-            return p
 
         def _free(ptr, ctx):
             with self._mu:

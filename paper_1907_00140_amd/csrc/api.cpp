@@ -475,6 +475,9 @@ void chl_build_opts_default(chl_build_opts* o) {
 
 int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
               const chl_allocator* alloc, void* stream, chl_labels** out) {
+    // launches are checked with hipGetLastError: drop an error that an
+    // earlier call on this thread left behind
+    (void)hipGetLastError();
     try {
         return chl_build_impl(g, order, opts, alloc, stream, out, false);
     } catch (...) {
@@ -484,6 +487,7 @@ int chl_build(const chl_graph* g, const int32_t* order, const chl_build_opts* op
 
 int chl_build_directed(const chl_graph* g, const int32_t* order, const chl_build_opts* opts,
                        const chl_allocator* alloc, void* stream, chl_labels** out) {
+    (void)hipGetLastError();
     try {
         return chl_build_directed_impl(g, order, opts, alloc, stream, out);
     } catch (...) {
@@ -542,6 +546,7 @@ int chl_query(const chl_labels* hc, const int32_t* pairs, int64_t q, int64_t* ou
     if (q == 0) return CHL_OK;
     chl_labels* h = const_cast<chl_labels*>(hc);
     hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();
     // the error word is per handle: concurrent queries on one handle serialise here
     std::lock_guard<std::mutex> lk(h->qmu);
     HIPCHK(hipMemsetAsync(h->qerr, 0, 4, st));

@@ -44,6 +44,7 @@ extern "C" int chl_microbench_atomic_min(void* buf, int64_t words, int key_bits,
     if (!buf || words < 1 || (key_bits != 32 && key_bits != 64) || ops < 1 || !ms || !done)
         return CHL_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
+    (void)hipGetLastError();   // the launch below is checked with hipGetLastError
     const int64_t threads = 256 * 8192;
     const int64_t per = std::max<int64_t>(1, ops / threads);
     hipEvent_t e0, e1;

@@ -330,6 +330,7 @@ using namespace chl;
 
 extern "C" int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32_t* parent, int32_t* slot,
                                   void* stream) {
+    (void)hipGetLastError();   // launches are checked with hipGetLastError
     if (!h || !g || h->directed || g->n != h->n || g->n_arcs < 0 || !g->row_ptr) return CHL_ERR_INVALID_ARG;
     if (g->n_arcs > 0 && (!g->col || !g->w)) return CHL_ERR_INVALID_ARG;
     if (h->total > 0 && (!parent || !slot)) return CHL_ERR_INVALID_ARG;
@@ -353,6 +354,7 @@ extern "C" int chl_labels_parents(const chl_labels* h, const chl_graph* g, int32
 extern "C" int chl_query_path_hops(const chl_labels* h, const int32_t* parent, const int32_t* slot,
                                    const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
                                    void* stream) {
+    (void)hipGetLastError();   // launches are checked with hipGetLastError
     if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !hops || !parent || !slot))) return CHL_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
     if (q == 0) {
@@ -413,6 +415,7 @@ void* noalloc_scratch() {
 extern "C" int chl_query_path_hops_noalloc(const chl_labels* h, const int32_t* parent, const int32_t* slot,
                                            const int32_t* pairs, int64_t q, int64_t* hops, int64_t* path_off,
                                            void* stream) {
+    (void)hipGetLastError();   // launches are checked with hipGetLastError
     if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !hops || !parent || !slot))) return CHL_ERR_INVALID_ARG;
     if (q > CHL_NOALLOC_MAX_PAIRS) return CHL_ERR_INVALID_ARG;
     hipStream_t st = (hipStream_t)stream;
@@ -442,6 +445,7 @@ extern "C" int chl_query_path_hops_noalloc(const chl_labels* h, const int32_t* p
 extern "C" int chl_query_paths(const chl_labels* h, const int32_t* parent, const int32_t* slot,
                                const int32_t* pairs, int64_t q, const int64_t* path_off, int32_t* path,
                                void* stream) {
+    (void)hipGetLastError();   // launches are checked with hipGetLastError
     if (!h || h->directed || q < 0 || (q > 0 && (!pairs || !parent || !slot || !path_off))) return CHL_ERR_INVALID_ARG;
     if (q == 0) return CHL_OK;
     hipStream_t st = (hipStream_t)stream;

@@ -143,6 +143,13 @@ struct Batch {
     hipEvent_t ev{};
     bool busy = false;
     std::vector<std::pair<int32_t, int64_t>> who;  // (block, query index)
+    double t_launch = 0;     // server time the batch was queued on the device
+    double t_oldest = 0;     // earliest scheduled arrival among its queries
+};
+
+// One row of the server's trace (chl_server_trace).
+struct TraceRow {
+    double kind, t0, t1, t2, size;
 };
 
 }  // namespace
@@ -171,6 +178,7 @@ struct chl_server {
     clk::time_point t0;
     std::condition_variable done_cv;
     bool all_done = false;
+    std::vector<TraceRow> trace;   // batches and builds of the last run (under mu for builds)
 
     double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
     void dispatch_loop();
@@ -194,6 +202,7 @@ void chl_server::run_build(size_t idx, int slot) {
     hipStream_t s = bs[slot];
     StreamAlloc* a = ba[slot].get();
     a->start((int64_t)b.footprint);
+    const double t_admit = now();
     chl_allocator al{StreamAlloc::alloc, StreamAlloc::release, a};
     int code = CHL_OK;
     int64_t* d_row = nullptr;
@@ -228,15 +237,20 @@ void chl_server::run_build(size_t idx, int slot) {
         if (p) StreamAlloc::release(p, a);
     (void)hipStreamSynchronize(s);
     double tc = now();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        trace.push_back({1.0, b.t, t_admit, tc, (double)b.n});
+    }
     const bool refused = code == CHL_ERR_OOM && a->refused;
     const int64_t peak = a->peak;
     budget_used -= a->finish();
     std::lock_guard<std::mutex> lk(mu);
     bs_busy[slot] = false;
-    if (refused && b.attempts < 4) {
+    if (refused && b.attempts < 4 && b.footprint < o.mem_budget) {
         // the estimate was too small and other builds held the rest of the
-        // budget: queue the request again, charged with what it reached
-        b.footprint = std::max<size_t>(2 * (size_t)peak, 2 * b.footprint);
+        // budget: queue the request again with a larger estimate (at most
+        // the whole budget: then it runs alone)
+        b.footprint = std::min<size_t>(o.mem_budget, std::max<size_t>(2 * b.footprint, (size_t)peak * 5 / 4));
         b.started = false;
         return;
     }
@@ -261,6 +275,10 @@ void chl_server::dispatch_loop() {
         for (Batch& B : batch) {
             if (!B.busy || hipEventQuery(B.ev) != hipSuccess) continue;
             double tc = now();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                trace.push_back({0.0, B.t_oldest, B.t_launch, tc, (double)B.who.size()});
+            }
             for (size_t j = 0; j < B.who.size(); j++) {
                 QBlock& qb = qblocks[B.who[j].first];
                 int64_t i = B.who[j].second;
@@ -334,6 +352,9 @@ void chl_server::dispatch_loop() {
             }
             (void)hipMemcpyAsync(B.h_out, B.d_out, (size_t)fill * 8, hipMemcpyDeviceToHost, qs);
             (void)hipEventRecord(B.ev, qs);
+            B.t_launch = now();
+            B.t_oldest = qblocks[B.who[0].first].t[B.who[0].second];
+            for (auto& w : B.who) B.t_oldest = std::min(B.t_oldest, qblocks[w.first].t[w.second]);
             B.busy = true;
             idle = false;
         }
@@ -478,6 +499,22 @@ int chl_server_submit_build(chl_server* s, int32_t n, int64_t n_arcs, const int6
     return CHL_OK;
 }
 
+int chl_server_trace(chl_server* s, double* rows, int64_t cap, int64_t* count) {
+    if (!s || !count || cap < 0 || (cap > 0 && !rows)) return CHL_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *count = (int64_t)s->trace.size();
+    const int64_t k = std::min<int64_t>(cap, (int64_t)s->trace.size());
+    for (int64_t i = 0; i < k; i++) {
+        const TraceRow& r = s->trace[i];
+        rows[5 * i + 0] = r.kind;
+        rows[5 * i + 1] = r.t0;
+        rows[5 * i + 2] = r.t1;
+        rows[5 * i + 3] = r.t2;
+        rows[5 * i + 4] = r.size;
+    }
+    return CHL_OK;
+}
+
 size_t chl_server_budget_peak(const chl_server* s) {
     return s ? (size_t)s->budget_peak.load() : 0;
 }
@@ -493,6 +530,7 @@ int chl_server_start(chl_server* s) {
     if (s->running) return CHL_ERR_INVALID_ARG;
     s->running = true;
     s->all_done = false;
+    s->trace.clear();
     s->t0 = clk::now();
     s->disp = std::thread(&chl_server::dispatch_loop, s);
     return CHL_OK;

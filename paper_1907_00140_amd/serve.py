@@ -80,6 +80,16 @@ class Server:
     def budget_peak(self) -> int:
         return int(self.lib.chl_server_budget_peak(self._h))
 
+    def trace(self):
+        """Rows (kind, t0, t1, t2, size) of the last run: kind 0 = query batch
+        (earliest arrival, queued, completed, queries), 1 = build (arrival,
+        admitted, completed, vertices)."""
+        n = C.c_int64()
+        _check(self.lib.chl_server_trace(self._h, None, 0, C.byref(n)), "chl_server_trace")
+        rows = np.zeros((max(n.value, 1), 5), np.float64)
+        _check(self.lib.chl_server_trace(self._h, rows.ctypes.data, n.value, C.byref(n)), "chl_server_trace")
+        return rows[:n.value]
+
     def start(self):
         _check(self.lib.chl_server_start(self._h), "chl_server_start")
 

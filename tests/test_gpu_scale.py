@@ -211,5 +211,5 @@ def test_capped_allocator_oom():
             off, hub, dist = (t.numpy() for t in L.export("cpu"))
             assert_same_labels(off, hub, dist, ref, "cap %d" % cap)
             L.free()
-        assert al.live_bytes() == 0, "cap %d: %d bytes not returned" % (cap, al.live_bytes())
+        assert al.live_bytes == 0, "cap %d: %d bytes not returned" % (cap, al.live_bytes)
     assert seen == {"oom", "ok"}

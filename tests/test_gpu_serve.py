@@ -102,28 +102,35 @@ def test_allocator_honoured():
         ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
         assert_same_labels(off.numpy(), hub.numpy(), dist.numpy(), ref, "built with the caller's allocator")
     srv.close()
-    assert al.live_bytes() == 0, "the server kept memory of the caller's allocator"
+    assert al.live_bytes == 0, "the server kept memory of the caller's allocator"
 
 
 def test_budget_never_overrun():
     """Builds whose labels outgrow the admission estimate (a grid: hundreds of
-    labels per vertex) charge the rest while they run; two of them together
-    need more than the budget, so one is queued again and runs after the
+    labels per vertex) charge the rest while they run. With a budget of 1.5
+    times what one build reaches alone, two builds submitted together do not
+    fit side by side: one is refused memory, queued again and run after the
     other. Both complete, equal to the same build alone, and the builds in
     flight never held more than the budget."""
     from paper_1907_00140_amd import chl, serve
-    c = gg.make_config("grid256x256_3")
+    c = gg.make_config("grid128x128_3")
     alone = [x.numpy() for x in chl.build(c["row_ptr"], c["col"], c["w"], c["order"]).export("cpu")]
-    probe = serve.Server(mem_budget=1 << 20, build_streams=2, build_wg=64)
-    est = probe.footprint(c["n"], len(c["col"]))
-    probe.close()
-    budget = 3 * est
+    srv = serve.Server(mem_budget=8 << 30, build_streams=2, build_wg=64)
+    est = srv.footprint(c["n"], len(c["col"]))
+    tk = srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.0)
+    srv.start()
+    srv.wait()
+    assert tk.status.value == 0
+    one = srv.budget_peak()
+    srv.close()
+    assert one > est, "the grid build did not outgrow its estimate (%d <= %d)" % (one, est)
+    budget = int(1.5 * one)
     srv = serve.Server(mem_budget=budget, build_streams=2, build_wg=64)
     tks = [srv.submit_build(c["row_ptr"], c["col"], c["w"], c["order"], 0.0) for _ in range(2)]
     srv.start()
     srv.wait()
-    _say("estimate %d MB, budget %d MB, peak charged %d MB, latencies %s" % (
-        est >> 20, budget >> 20, srv.budget_peak() >> 20, [round(t.lat.value, 4) for t in tks]))
+    _say("estimate %d MB, one build %d MB, budget %d MB, peak charged %d MB, latencies %s" % (
+        est >> 20, one >> 20, budget >> 20, srv.budget_peak() >> 20, [round(t.lat.value, 4) for t in tks]))
     assert srv.budget_peak() <= budget
     for tk in tks:
         assert tk.status.value == 0, tk.status.value
