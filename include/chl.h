@@ -140,6 +140,13 @@ typedef struct chl_build_opts {
                                 workgroup per tree; 2..16: that many, capped so
                                 that every team of a launch is resident (a
                                 cooperative launch). Same labels either way. */
+    int32_t group_levels;    /* batched form: 0: levels of 16 to 512 trees grow
+                                in groups of 16 trees of consecutive roots, one
+                                group per team of workgroups, their per-vertex
+                                keys side by side (one cache line holds a
+                                vertex's keys of all 16 trees); -1: each tree
+                                alone (teams or one workgroup). Ignored when
+                                team_wgs is 1. Same labels either way. */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */
@@ -318,7 +325,9 @@ typedef struct chl_stats {
     int64_t levels;
     int64_t level_end[CHL_MAX_LEVELS];
     double level_ms[CHL_MAX_LEVELS];   /* device time of each level's tree launches */
-    int64_t level_teams[CHL_MAX_LEVELS];  /* workgroups per tree of the level (1: batched kernel) */
+    int64_t level_teams[CHL_MAX_LEVELS];  /* workgroups per tree of the level (1: batched
+                                             kernel); -w: groups of 16 trees, w
+                                             workgroups per group */
 } chl_stats;
 
 /* Totals into *totals (host, may be NULL). per_root (may be NULL) receives

@@ -50,7 +50,8 @@ class CBuildOpts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("roots_in_flight", C.c_int32), ("wg_size", C.c_int32),
                 ("delta", C.c_int64), ("early_term", C.c_int32), ("stats", C.c_int32),
                 ("autotune", C.c_int32), ("root_count", C.c_int32), ("root_begin", C.c_int32),
-                ("root_stride", C.c_int32), ("prune_hubs", C.c_int32), ("team_wgs", C.c_int32)]
+                ("root_stride", C.c_int32), ("prune_hubs", C.c_int32), ("team_wgs", C.c_int32),
+                ("group_levels", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -365,7 +366,7 @@ class Labels:
 
 def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, delta=0,
           early_term=True, stats=True, autotune=True, roots=None, prune_hubs=0, team_wgs=0,
-          stream=None, allocator="torch", directed=False):
+          stream=None, allocator="torch", directed=False, groups=True):
     """chl_build over a symmetric CSR (row_ptr int64, col int32, w int32) and a
     ranking order (order[0] most important). roots = (begin, count, stride)
     restricts the build to those root rank positions. directed=True: the CSR
@@ -391,6 +392,7 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
         o.root_begin, o.root_count, o.root_stride = (int(x) for x in roots)
     o.prune_hubs = int(prune_hubs)
     o.team_wgs = int(team_wgs)
+    o.group_levels = 0 if groups else -1
     al = allocator if isinstance(allocator, TorchAllocator) else default_allocator() if allocator == "torch" else None
     out = C.c_void_p()
     f = lib.chl_build_directed if directed else lib.chl_build

@@ -286,14 +286,59 @@ struct TeamCfg {
     int32_t* far2 = nullptr;      // [nteams][n]
 };
 
-// Run the batched kernel (or the team kernel when team is set) over roots
+// Groups of GROUP_TREES trees grown together by teams of workgroups (one
+// group per team at a time), their keys vertex-major.
+struct GroupCfg {
+    int size = 0;                 // workgroups per team
+    int ngroups = 0;              // teams
+    Slots s{};                    // key: ngroups * n * GROUP_TREES keys; touched, lists as for teams
+    long long* gstate = nullptr;  // [ngroups][GROUP_WORDS]
+    int32_t* far2 = nullptr;      // [ngroups][n]
+    uint32_t* gmask = nullptr;    // [ngroups][2n]
+};
+
+size_t group_bytes(int32_t n, int key_bits) {
+    return (size_t)n * ((size_t)GROUP_TREES * key_bits / 8 + 8 + 16 + 4) + (size_t)GROUP_WORDS * 8;
+}
+
+int alloc_groups(Arena& A, Build& B, int ngroups, GroupCfg& gc, hipStream_t st) {
+    const size_t n = (size_t)B.n;
+    const size_t kb = (size_t)B.key_bits / 8;
+    gc.s.k = ngroups;
+    gc.s.stride = B.n;
+    gc.s.fstride = 0;
+    gc.s.flags = nullptr;
+    gc.s.key = A.get<uint8_t>((size_t)ngroups * n * GROUP_TREES * kb);
+    gc.s.touched = A.get<int32_t>((size_t)ngroups * n);
+    gc.s.lists = A.get<int32_t>((size_t)ngroups * 3 * n);
+    gc.far2 = A.get<int32_t>((size_t)ngroups * n);
+    gc.gmask = A.get<uint32_t>((size_t)ngroups * 2 * n);
+    gc.gstate = A.get<long long>((size_t)ngroups * GROUP_WORDS);
+    if (!gc.s.key || !gc.s.touched || !gc.s.lists || !gc.far2 || !gc.gmask || !gc.gstate) return CHL_ERR_OOM;
+    HIPCHK(hipMemsetAsync(gc.s.key, 0xFF, (size_t)ngroups * n * GROUP_TREES * kb, st));
+    HIPCHK(hipMemsetAsync(gc.gmask, 0, (size_t)ngroups * 2 * n * 4, st));
+    return 0;
+}
+
+void free_groups(Arena& A, GroupCfg& gc) {
+    A.drop(gc.s.key);
+    A.drop(gc.s.touched);
+    A.drop(gc.s.lists);
+    A.drop(gc.far2);
+    A.drop(gc.gmask);
+    A.drop(gc.gstate);
+    gc = GroupCfg{};
+}
+
+// Run the batched kernel (or the team kernel when team is set, the group
+// kernel when grp is set) over roots
 // (NULL = all, in rank order; roots_in_place: the list is already in B.roots
 // on the stream) until every root has emitted, growing the pool when it
 // fills up.
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
                 const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
                 int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr,
-                bool roots_in_place = false) {
+                bool roots_in_place = false, const GroupCfg* grp = nullptr) {
     std::vector<int32_t> pending;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
@@ -305,15 +350,20 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
     for (;;) {
         HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
         HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
-        TreeParams p = params(B, s, delta, early, dev_roots, nroots, root_base);
+        TreeParams p = params(B, grp ? grp->s : s, delta, early, dev_roots, nroots, root_base);
         HostCtl* hc = host_ctl();
         if (!hc) return CHL_ERR_HIP;
         if (team) HIPCHK(hipMemsetAsync(team->tstate, 0, (size_t)team->nteams * TEAM_WORDS * 8, st));
+        if (grp) HIPCHK(hipMemsetAsync(grp->gstate, 0, (size_t)grp->ngroups * GROUP_WORDS * 8, st));
         {
             // the launch is timed by events; the control words are read back
             // behind it, and one synchronisation completes both
             Timer tk(st);
-            if (team) {
+            if (grp) {
+                if (launch_tree_group(p, B.key_bits, 1024, grp->size, grp->ngroups, grp->gstate, grp->far2,
+                                      grp->gmask, st))
+                    return CHL_ERR_HIP;
+            } else if (team) {
                 if (launch_tree_team(p, B.key_bits, wg, team->size, team->nteams, team->tstate, team->far2, st))
                     return CHL_ERR_HIP;
             } else if (launch_tree_batched(p, B.key_bits, wg, phase, st)) {
@@ -690,12 +740,43 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
         tc.tstate = tstate;
         return &tc;
     };
+    // Levels of 64 to 256 trees run as groups of GROUP_TREES trees with
+    // vertex-major keys (the trees of a level reach largely the same
+    // vertices), when the groups' state fits GROUP_MAX_BYTES. Measured on
+    // R-MAT 20 against one tree per team: levels [64,128), [128,256) and
+    // [256,512) take 26.8, 32.4 and 26.1 ms instead of 32.0, 44.6 and 38.6;
+    // the levels of 16 and 32 trees, whose few groups span 128 to 256
+    // workgroups each, are slower as groups (their hubs land on one workgroup
+    // for all 16 trees, and every round's barrier has 128-256 members), and
+    // so are levels of 512 trees, which share few vertices. The group
+    // buffers are kept across levels and grown when a level needs more.
+    GroupCfg gcfg;
+    const bool groups_on = o.group_levels >= 0 && o.team_wgs != 1 && lwg == 1024;
+    constexpr size_t GROUP_MAX_BYTES = (size_t)8 << 30;
+    auto group_for = [&](int32_t nr, int32_t pbound, GroupCfg& gc) -> const GroupCfg* {
+        if (!groups_on || nr < 4 * GROUP_TREES || nr > 256 || pbound > GROUP_MAX_PREFIX) return nullptr;
+        const int ng = (nr + GROUP_TREES - 1) / GROUP_TREES;
+        if ((size_t)ng * group_bytes(n, B.key_bits) > GROUP_MAX_BYTES) return nullptr;
+        const int cap = group_capacity(B.key_bits, pbound);
+        if (cap < ng) return nullptr;
+        if (gcfg.ngroups < ng) {
+            if (gcfg.ngroups) free_groups(A, gcfg);
+            if (alloc_groups(A, B, ng, gcfg, st)) return nullptr;
+        }
+        gc = gcfg;
+        gc.ngroups = ng;
+        gc.s.k = ng;
+        gc.size = std::max(1, std::min(256, cap / ng));
+        return &gc;
+    };
     TeamCfg tc0;
-    const TeamCfg* tcp0 = team_for(g, tc0);
+    GroupCfg gc0;
+    const GroupCfg* gcp0 = group_for(g, 0, gc0);
+    const TeamCfg* tcp0 = gcp0 ? nullptr : team_for(g, tc0);
     double ms0 = B.kernel_ms;
-    if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0, tcp0))
+    if (int r = run_batched(A, B, s1, lwg, dl, o.early_term, nullptr, g, st, &launches, 2, 0, tcp0, false, gcp0))
         return r;
-    B.record_level(g, B.kernel_ms - ms0, tcp0 ? tcp0->size : 1);
+    B.record_level(g, B.kernel_ms - ms0, gcp0 ? -gcp0->size : tcp0 ? tcp0->size : 1);
     if (int r = regroup()) return r;
     unsigned long long level_labels = B.cursor_base;
     grown = g;
@@ -755,8 +836,10 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             const int32_t g2 = std::min<int32_t>(gmax, f * g);
             B.pbound = g;
             TeamCfg tc;
+            GroupCfg gc;
             const unsigned long long before = B.cursor_base;
-            const TeamCfg* tcp = team_for(g2 - g, tc);
+            const GroupCfg* gcp = group_for(g2 - g, g, gc);
+            const TeamCfg* tcp = gcp ? nullptr : team_for(g2 - g, tc);
             // a level of more trees than slots runs them in waves, and a large
             // tree that starts late sets the level's end: start the trees
             // whose roots carry the most prefix labels first (a directed
@@ -765,14 +848,16 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             // level [128, 1024): rank correlation 0.45 with the tree's
             // duration; builds 4.5% faster, the directed R-MAT 16 build 5%).
             // The order is computed and sorted on the stream, into B.roots.
-            const bool ordered = !tcp;
+            // (a group keeps rank order: roots close in rank reach the same
+            // vertices)
+            const bool ordered = !tcp && !gcp;
             if (ordered && launch_level_order(B.poff, g, g2, B.partner, lkeys, loff, B.roots, st))
                 return CHL_ERR_HIP;
             const double ms1 = B.kernel_ms;
             if (int r = run_batched(A, B, s1, lwg, dl1, o.early_term, nullptr, g2 - g, st, &launches, 2, g, tcp,
-                                    ordered))
+                                    ordered, gcp))
                 return r;
-            B.record_level(g2, B.kernel_ms - ms1, tcp ? tcp->size : 1);
+            B.record_level(g2, B.kernel_ms - ms1, gcp ? -gcp->size : tcp ? tcp->size : 1);
             if (int r = regroup()) return r;
             level_labels = B.cursor_base - before;
             g = g2;
@@ -781,6 +866,7 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
         B.pbound = g;
     }
     free_slots(A, s1);
+    if (gcfg.ngroups) free_groups(A, gcfg);
     if (tfar2) A.drop(tfar2);
     if (tstate) A.drop(tstate);
     B.grown = grown;
@@ -811,6 +897,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.root_count < 0) return CHL_ERR_INVALID_ARG;
     if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
     if (o.team_wgs < 0 || o.team_wgs > 16) return CHL_ERR_INVALID_ARG;
+    if (o.group_levels < -1 || o.group_levels > 0) return CHL_ERR_INVALID_ARG;
     if (o.root_count > 0) {
         if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
         if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;

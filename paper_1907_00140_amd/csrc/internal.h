@@ -153,6 +153,19 @@ constexpr int TEAM_WORDS = 32;
 int launch_tree_team(const TreeParams& p, int key_bits, int wg, int team_size, int nteams,
                      long long* tstate, int32_t* far2, hipStream_t st);
 int team_capacity(int key_bits, int wg);   // co-resident workgroups of the team kernel
+// Groups: ngroups teams of team_size 1024-thread workgroups; each team grows
+// GROUP_TREES trees of consecutive queue entries at a time, their keys vertex-
+// major (group slot i: s.key holds n * GROUP_TREES keys at i * s.stride *
+// GROUP_TREES; touched / lists as for teams; far2 [i * n]; gmask 4n words at
+// i * 2n: two mask words per vertex, zero between groups; gstate GROUP_WORDS
+// words per team, zeroed before the launch). Cooperative launch; pbound <=
+// GROUP_MAX_PREFIX.
+constexpr int GROUP_TREES = 16;
+constexpr int GROUP_WORDS = 256;
+constexpr int GROUP_MAX_PREFIX = 1024;
+int launch_tree_group(const TreeParams& p, int key_bits, int wg, int team_size, int ngroups, long long* gstate,
+                      int32_t* far2, uint32_t* gmask, hipStream_t st);
+int group_capacity(int key_bits, int pbound);   // co-resident workgroups of the group kernel
 
 // assemble.hip
 int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t total,

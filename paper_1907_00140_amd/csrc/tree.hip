@@ -1020,6 +1020,532 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
     }
 }
 
+// ---------------------------------------------------------------- groups
+// A team of W workgroups grows GT trees of consecutive roots together: the
+// trees of a pruning level whose roots are close in rank reach largely the
+// same vertices, at about the same distances. Their per-vertex state is kept
+// vertex-major, key[v * GT + b] being tree b's key of v, so the GT keys of a
+// vertex share one cache line (64-bit keys: 128 B), and one pass over a
+// frontier vertex's arcs relaxes them for every tree that has the vertex
+// pending. A random access to the key array then serves up to GT trees
+// instead of one, and u's prefix labels, read by the pruning test, are read
+// once for the trees that reach u in the same round.
+//
+// Per vertex v, besides the keys: mask[v] holds, per near list (bits 0-15
+// list 0, 16-31 list 1, alternating by round as in the other forms), the
+// trees that have v pending in it; fmask[v] holds the trees with v pending
+// in the far list (bits 0-15), FAR_IN (v is in the far list) and TOUCHED (v
+// is in the touched list). A vertex is listed once per list whatever the
+// number of trees that have it pending. The bucket bound T is shared by the
+// group (the next bucket is the one of the smallest pending distance of any
+// tree); each tree keeps its own early-termination test and stops on its
+// own. Labels and statistics are those of each tree alone.
+constexpr int GT = GROUP_TREES;
+static_assert(GT == 16, "the masks hold 16 trees per half word");
+constexpr uint32_t GBITS = (1u << GT) - 1;
+constexpr uint32_t GF_FAR_IN = 1u << 16, GF_TOUCHED = 1u << 17;
+enum {
+    GW_CNT0 = 0, GW_CNT1x, GW_CNT2x,      // near list counts, rotating by round % 3
+    GW_FARL = 3, GW_FAR2L, GW_TOUCHEDL,   // far list, filtered far list, touched list
+    GW_MINP = 6, GW_TB = 8,              // smallest kept far distance, bucket bound
+    GW_NLABT = 10, GW_BASEP, GW_FILLP,    // labels of the group, pool base, fill
+    GW_BAR = T_BAR, GW_ABORT = T_ABORT,  // barrier words (shared with team_sync)
+    GW_ROOT = 32,                       // per-tree words from here, GT each:
+    GW_UMAX = GW_ROOT + GT, GW_FCLEAN = GW_UMAX + GT, GW_SMIN = GW_FCLEAN + GT,  // SMIN: 2 parities
+    GW_SCL = GW_SMIN + 2 * GT, GW_CLEAN = GW_SCL + 2 * GT, GW_SETTLEDB = GW_CLEAN + GT, GW_ARCSB = GW_SETTLEDB + GT,
+    GW_NLABB = GW_ARCSB + GT, GW_KEPTM = GW_NLABB + GT,   // trees with far entries kept at the last filter
+    GW_WORDS_USED = GW_KEPTM + 1
+};
+static_assert(GW_WORDS_USED <= GROUP_WORDS, "group words");
+static_assert(T_BAR < GW_ROOT && T_ABORT < GW_ROOT && T_BAR > GW_FILLP, "group word layout");
+
+template <typename K, int WG>
+struct GroupLds {
+    int64_t beg[WG];          // row start of the chunk's vertices
+    int32_t vtx[WG];          // the vertices
+    uint32_t msk[WG];         // trees to expand at each of them
+    uint32_t off[WG];         // exclusive scan of deg * popcount(msk)
+    uint32_t wsum[WG / 64];
+    unsigned long long red64[WG / 64];
+    int32_t hroot[GT];
+    unsigned long long lmin[GT], lumax[GT];
+    uint32_t lcl[GT], lfcl[GT];
+    unsigned long long lset[GT], larc[GT], lnl[GT];
+    int ok;
+};
+
+// work items in flight per thread
+constexpr int GROUP_ILP = 4;
+
+// What the relaxation of a group's work items needs besides the launch
+// parameters.
+template <typename K>
+struct GroupCtx {
+    K* key;
+    uint32_t* mask;
+    uint32_t* fmask;
+    int32_t* touched;
+    int32_t* next;
+    int32_t* far;
+    long long* tw;
+    int64_t T;
+    uint32_t nsh;     // bit offset of the next round's half of mask
+    uint32_t pb;      // pruning prefix (0: none)
+    int32_t n;
+    int it;
+};
+
+// Relax the work items [e_lo, e_hi) of a round, GROUP_ILP per thread at a
+// time; decode(e, arc, tree, key of the expanded vertex) gives item e.
+// Improved (vertex, tree) pairs go to the next near list or the far list,
+// vertices reached for the first time by any tree to the touched list; the
+// per-tree largest clean distance, clean far pushes and counts accumulate
+// in LDS.
+template <typename K, int WG, bool PRUNE, typename D>
+__device__ __forceinline__ void group_relax(const TreeParams& p, const GroupCtx<K>& cx, GroupLds<K, WG>& S,
+                                            const uint32_t* dh, uint32_t e_lo, uint32_t e_hi, D decode) {
+    constexpr int SC = __HIP_MEMORY_SCOPE_AGENT;
+    typedef unsigned long long ull;
+    for (uint32_t e0 = e_lo + threadIdx.x; e0 < e_hi; e0 += WG * GROUP_ILP) {
+        int tb[GROUP_ILP];
+        uint64_t a[GROUP_ILP];
+        K kv[GROUP_ILP], seen[GROUP_ILP];
+#pragma unroll
+        for (int j = 0; j < GROUP_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            a[j] = 0; tb[j] = 0; kv[j] = 0;
+            if (e < e_hi) decode(e, a[j], tb[j], kv[j]);
+        }
+        // (lanes of one arc read the key line of its target once)
+#pragma unroll
+        for (int j = 0; j < GROUP_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            seen[j] = e < e_hi ? ld<SC>(&cx.key[(int64_t)(a[j] >> 32) * GT + tb[j]]) : (K)0;
+        }
+#pragma unroll
+        for (int j = 0; j < GROUP_ILP; j++) {
+            const uint32_t e = e0 + j * WG;
+            const bool valid = e < e_hi;
+            const int b = tb[j];
+            const int32_t u = (int32_t)(a[j] >> 32);
+            const int32_t h = S.hroot[b];
+            const uint64_t nd = (uint64_t)(kv[j] >> 1) + (uint32_t)a[j];
+            const K nk = pack<K>(nd, (uint32_t)(kv[j] & 1) & (uint32_t)(u > h));
+            bool cand = valid && nk < seen[j];
+            if (PRUNE && cand && cx.pb) {
+                // rank-prefix pruning (Section 4.3), as in the other forms,
+                // with this tree's root distances
+                const uint32_t* dhb = dh + (int64_t)b * cx.pb;
+                const int64_t lb = p.poff[u], le = p.poff[u + 1];
+                for (int64_t i = lb; i < le && cand; i += 4) {
+                    uint64_t lx[4];
+#pragma unroll
+                    for (int z = 0; z < 4; z++) lx[z] = i + z < le ? p.plab[i + z] : ~0ull;
+#pragma unroll
+                    for (int z = 0; z < 4; z++) {
+                        const uint32_t x = (uint32_t)(lx[z] >> 32);
+                        if (x >= cx.pb) continue;
+                        const uint32_t ax = dhb[x];
+                        if (ax != 0xFFFFFFFFu && (uint64_t)ax + (uint32_t)lx[z] <= nd) cand = false;
+                    }
+                }
+            }
+            K old = seen[j];
+            if (cand) old = amin<SC>(&cx.key[(int64_t)u * GT + b], nk);
+            const bool imp = cand && nk < old;
+            const bool tonear = imp && (int64_t)nd < cx.T;
+            bool pnear = false, pfar = false, ptouch = false;
+            if (imp) {
+                if (nk & 1) {
+                    atomicMax(&S.lumax[b], (ull)nd);
+                    if (!tonear) atomicAdd(&S.lfcl[b], 1u);
+                }
+                if (tonear) {
+                    const uint32_t bit = 1u << (cx.nsh + (uint32_t)b);
+                    const uint32_t o = __hip_atomic_fetch_or(&cx.mask[u], bit, __ATOMIC_RELAXED, SC);
+                    pnear = ((o >> cx.nsh) & GBITS) == 0;
+                } else {
+                    const uint32_t o = aor<SC>(&cx.fmask[u], (1u << b) | GF_FAR_IN);
+                    pfar = (o & GF_FAR_IN) == 0;
+                }
+                if (old == KeyTraits<K>::INF) {
+                    const uint32_t o = aor<SC>(&cx.fmask[u], GF_TOUCHED);
+                    ptouch = (o & GF_TOUCHED) == 0;
+                }
+            }
+            int64_t q = wave_append(ptouch, (ull*)&cx.tw[GW_TOUCHEDL]);
+            if (ptouch && q < cx.n) lput<SC>(&cx.touched[q], u);
+            q = wave_append(pnear, (ull*)&cx.tw[GW_CNT0 + (cx.it + 1) % 3]);
+            if (pnear && q < cx.n) lput<SC>(&cx.next[q], u);
+            q = wave_append(pfar, (ull*)&cx.tw[GW_FARL]);
+            if (pfar && q < cx.n) lput<SC>(&cx.far[q], u);
+        }
+    }
+}
+
+__device__ __forceinline__ int nth_bit(uint32_t m, int j) {
+    for (int k = 0; k < j; k++) m &= m - 1;
+    return __ffs(m) - 1;
+}
+
+template <typename K, int WG, bool PRUNE>
+__global__ __launch_bounds__(WG) void k_tree_group(TreeParams p, int W, long long* gstate, int32_t* far2_all,
+                                                   uint32_t* gmask_all) {
+    constexpr int SC = __HIP_MEMORY_SCOPE_AGENT;
+    typedef unsigned long long ull;
+    __shared__ GroupLds<K, WG> S;
+    extern __shared__ uint32_t dh[];     // [GT][pbound]: each tree's root distances to the prefix hubs
+    const int tid = threadIdx.x;
+    const int team = blockIdx.x / W, trank = blockIdx.x % W;
+    const int64_t tgtid = (int64_t)trank * WG + tid, tthreads = (int64_t)W * WG;
+    const bool leader = trank == 0 && tid == 0;
+    const int32_t n = p.g.n;
+    long long* tw = gstate + (int64_t)team * GROUP_WORDS;
+    K* key = (K*)p.s.key + (int64_t)team * p.s.stride * GT;
+    uint32_t* mask = gmask_all + (int64_t)team * 2 * p.s.stride;
+    uint32_t* fmask = mask + p.s.stride;
+    int32_t* touched = p.s.touched + (int64_t)team * p.s.stride;
+    int32_t* lists = p.s.lists + (int64_t)team * 3 * p.s.stride;
+    int32_t* far = lists + 2 * p.s.stride;
+    int32_t* far2 = far2_all + (int64_t)team * p.s.stride;
+    const int64_t delta = p.delta;
+    const long long INF = 0x7FFFFFFFFFFFFFFFll;
+    const uint32_t pb = PRUNE ? (uint32_t)p.pbound : 0u;
+    ull nb = 0;
+    uint64_t t_start = 0;
+
+    for (;;) {
+        // ---- the leader takes the next GT roots and sets up their trees
+        if (leader) {
+            int32_t c = 0x7FFFFFFF;
+            if (ld<SC>(p.stop) == 0) c = atomicAdd(p.next_root, GT);
+            for (int i = 0; i < GW_ROOT; i++)
+                if (i != GW_BAR && i != GW_ABORT) tws(tw, i, 0);
+            for (int i = GW_ROOT; i < GW_WORDS_USED; i++) tws(tw, i, 0);
+            tws(tw, GW_MINP, INF);
+            tws(tw, GW_TB, delta);
+            int32_t nr = 0;
+            for (int b = 0; b < GT; b++) {
+                tws(tw, GW_SMIN + b, INF);
+                tws(tw, GW_SMIN + GT + b, INF);
+                const int32_t q = c + b;
+                const int32_t r = c < p.nroots && q < p.nroots ? (p.roots ? p.roots[q] : p.root_base + q) : -1;
+                tws(tw, GW_ROOT + b, r);
+                if (r >= 0 && r < n) {
+                    st<SC>(&key[(int64_t)r * GT + b], pack<K>(0, 1));
+                    __hip_atomic_fetch_or(&mask[r], 1u << b, __ATOMIC_RELAXED, SC);
+                    aor<SC>(&fmask[r], GF_TOUCHED);
+                    lput<SC>(&lists[nr], r);
+                    lput<SC>(&touched[nr], r);
+                    nr++;
+                }
+            }
+            tws(tw, GW_CNT0, nr);
+            tws(tw, GW_TOUCHEDL, nr);
+            t_start = __builtin_amdgcn_s_memrealtime();
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        uint32_t alive = 0;
+        if (tid < GT) S.hroot[tid] = twl<int32_t>(tw, GW_ROOT + tid);
+        __syncthreads();
+        for (int b = 0; b < GT; b++)
+            if (S.hroot[b] >= 0) alive |= 1u << b;
+        if (!alive) return;
+        const uint32_t valid = alive;
+        if (PRUNE) {
+            // each tree's distances to the prefix hubs, from its root's
+            // prefix labels (a directed build reads the partner's)
+            for (int64_t x = tid; x < (int64_t)GT * pb; x += WG) dh[x] = 0xFFFFFFFFu;
+            __syncthreads();
+            const uint32_t px = (uint32_t)p.partner;
+            for (int b = 0; b < GT; b++) {
+                const int32_t h = S.hroot[b];
+                if (h < 0 || (uint32_t)h < pb) continue;
+                const int32_t hg = h ^ (int32_t)px;
+                for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
+                    const uint64_t lx = p.plab[i];
+                    const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                    if (x < pb && y < pb) dh[b * pb + y] = (uint32_t)lx;
+                }
+            }
+            __syncthreads();
+        }
+        uint32_t early_m = 0;
+        int it = 0;
+        for (;;) {
+            const int par = it & 1;
+            if (leader)
+                for (int b = 0; b < GT; b++) {
+                    tws(tw, GW_SMIN + (par ^ 1) * GT + b, INF);
+                    tws(tw, GW_SCL + (par ^ 1) * GT + b, 0);
+                }
+            const int64_t T = twl<int64_t>(tw, GW_TB);
+            const int32_t ncur = min(twl<int32_t>(tw, GW_CNT0 + it % 3), n);
+            const uint32_t sh = 16u * (uint32_t)par, nsh = 16u * (uint32_t)(par ^ 1);
+            int32_t* cur = lists + (int64_t)par * p.s.stride;
+            int32_t* next = lists + (int64_t)(par ^ 1) * p.s.stride;
+            if (ncur > 0) {
+                // ---- per-tree early termination between rounds (the test of
+                //      the other forms, for every tree with no clean far push)
+                uint32_t cand_stop = 0;
+                for (int b = 0; b < GT; b++)
+                    if ((alive >> b & 1) && twl<long long>(tw, GW_FCLEAN + b) == 0) cand_stop |= 1u << b;
+                if (p.early_term && cand_stop) {
+                    if (tid < GT) { S.lmin[tid] = ~0ull; S.lcl[tid] = 0; }
+                    __syncthreads();
+                    for (int64_t i = tgtid; i < ncur; i += tthreads) {
+                        const int32_t v = lget<SC>(&cur[i], n);
+                        uint32_t m = (ld<SC>(&mask[v]) >> sh) & cand_stop;
+                        while (m) {
+                            const int b = __ffs(m) - 1;
+                            m &= m - 1;
+                            const K kv = ld<SC>(&key[(int64_t)v * GT + b]);
+                            atomicMin(&S.lmin[b], (ull)(kv >> 1));
+                            if (kv & 1) atomicOr(&S.lcl[b], 1u);
+                        }
+                    }
+                    __syncthreads();
+                    if (tid < GT && (cand_stop >> tid & 1)) {
+                        if (S.lmin[tid] != ~0ull) atomicMin((ull*)&tw[GW_SMIN + par * GT + tid], S.lmin[tid]);
+                        if (S.lcl[tid]) atomicOr((ull*)&tw[GW_SCL + par * GT + tid], 1ull);
+                    }
+                    if (!team_sync(tw, W, nb, S, p.err)) return;
+                    uint32_t stopm = 0;
+                    for (int b = 0; b < GT; b++) {
+                        if (!(cand_stop >> b & 1)) continue;
+                        const ull smin = twl<ull>(tw, GW_SMIN + par * GT + b);
+                        const ull lb = smin < (ull)T ? smin : (ull)T;
+                        if (twl<ull>(tw, GW_SCL + par * GT + b) == 0 && lb > twl<ull>(tw, GW_UMAX + b)) stopm |= 1u << b;
+                    }
+                    // a stopped tree keeps its pending bits; every later read of
+                    // a mask is restricted to the trees still growing
+                    // (a tree that stops here still had near entries, or far ones)
+                    for (int b = 0; b < GT; b++)
+                        if ((stopm >> b & 1) && twl<ull>(tw, GW_SMIN + par * GT + b) != (ull)INF) early_m |= 1u << b;
+                    alive &= ~stopm;
+                    if (!alive) break;
+                }
+                // ---- relax: the near list split evenly over the team's
+                //      workgroups; each chunk's work items are (vertex, arc,
+                //      tree) triples, trees fastest, so that consecutive lanes
+                //      read the same arc and the same key line
+                const GroupCtx<K> cx{key, mask, fmask, touched, next, far, tw, T, nsh, pb, n, it};
+                const int32_t chunk = min(WG, (ncur + W - 1) / W);
+                if (tid < GT) { S.lumax[tid] = 0; S.lfcl[tid] = 0; S.lset[tid] = 0; S.larc[tid] = 0; }
+                __syncthreads();
+                for (int32_t base = trank * chunk; base < ncur; base += W * chunk) {
+                    const int32_t nv = min(chunk, ncur - base);
+                    uint32_t items = 0;
+                    if (tid < nv) {
+                        const int32_t v = lget<SC>(&cur[base + tid], n);
+                        const uint32_t old = __hip_atomic_fetch_and(&mask[v], ~(GBITS << sh), __ATOMIC_RELAXED, SC);
+                        const uint32_t m = (old >> sh) & alive;
+                        const int64_t b0 = p.g.row[v];
+                        const uint32_t deg = (uint32_t)(p.g.row[v + 1] - b0);
+                        for (uint32_t mm = m; mm;) {
+                            const int b = __ffs(mm) - 1;
+                            mm &= mm - 1;
+                            atomicAdd(&S.lset[b], 1ull);
+                            atomicAdd(&S.larc[b], (ull)deg);
+                        }
+                        S.beg[tid] = b0;
+                        S.vtx[tid] = v;
+                        S.msk[tid] = m;
+                        items = deg * (uint32_t)__popc(m);
+                    }
+                    uint32_t total;
+                    const uint32_t ex = block_scan<WG>(items, S.wsum, total);   // (synchronises the block)
+                    S.off[tid] = ex;
+                    __syncthreads();
+                    group_relax<K, WG, PRUNE>(p, cx, S, dh, 0, total, [&](uint32_t e, uint64_t& a, int& b, K& kv) {
+                        int lo = 0, hi = nv - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (S.off[mid] <= e) lo = mid; else hi = mid - 1;
+                        }
+                        const uint32_t m = S.msk[lo];
+                        const uint32_t pc = (uint32_t)max(1, __popc(m));
+                        const uint32_t r = e - S.off[lo];
+                        b = nth_bit(m, (int)(r % pc));
+                        a = p.g.arc[S.beg[lo] + r / pc];
+                        kv = ld<SC>(&key[(int64_t)S.vtx[lo] * GT + b]);
+                    });
+                    __syncthreads();
+                }
+                if (tid < GT) {
+                    if (S.lumax[tid]) atomicMax((ull*)&tw[GW_UMAX + tid], S.lumax[tid]);
+                    if (S.lfcl[tid]) atomicAdd((ull*)&tw[GW_FCLEAN + tid], (ull)S.lfcl[tid]);
+                    if (S.lset[tid]) atomicAdd((ull*)&tw[GW_SETTLEDB + tid], S.lset[tid]);
+                    if (S.larc[tid]) atomicAdd((ull*)&tw[GW_ARCSB + tid], S.larc[tid]);
+                }
+                if (leader) tws(tw, GW_CNT0 + (it + 2) % 3, 0);
+                if (!team_sync(tw, W, nb, S, p.err)) return;
+                it++;
+                continue;
+            }
+            // ---- bucket done: filter the far list into far2, keeping for each
+            //      vertex the trees whose key is still at or beyond T
+            const int32_t nfar = min(twl<int32_t>(tw, GW_FARL), n);
+            if (tid < GT) S.lcl[tid] = 0;
+            __syncthreads();
+            ull mymin = ~0ull;
+            for (int64_t i = tgtid; i < nfar; i += tthreads) {
+                const int32_t v = lget<SC>(&far[i], n);
+                const uint32_t fm = ld<SC>(&fmask[v]);
+                uint32_t m = fm & GBITS & alive, keep = 0;
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    const K kv = ld<SC>(&key[(int64_t)v * GT + b]);
+                    if ((int64_t)(kv >> 1) >= T) {
+                        keep |= 1u << b;
+                        mymin = min(mymin, (ull)(kv >> 1));
+                        if (kv & 1) atomicAdd(&S.lcl[b], 1u);
+                    }
+                }
+                // the far bits of trees no longer growing are dropped too
+                aand<SC>(&fmask[v], ~((GBITS & ~keep) | GF_FAR_IN));
+                if (keep) atomicOr((ull*)&tw[GW_KEPTM], (ull)keep);
+                const int64_t q = wave_append(keep != 0, (ull*)&tw[GW_FAR2L]);
+                if (keep && q < n) lput<SC>(&far2[q], v);
+            }
+            mymin = block_reduce<WG>(mymin, S.red64, ~0ull, [](ull x, ull y) { return x < y ? x : y; });
+            __syncthreads();
+            if (tid == 0 && mymin != ~0ull) atomicMin((ull*)&tw[GW_MINP], mymin);
+            if (tid < GT && S.lcl[tid]) atomicAdd((ull*)&tw[GW_CLEAN + tid], (ull)S.lcl[tid]);
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+            const int32_t nkeep = min(twl<int32_t>(tw, GW_FAR2L), n);
+            // a tree with no clean vertex left in the far list stops (the
+            // bucket-end test of the other forms)
+            if (p.early_term) {
+                uint32_t stopm = 0;
+                for (int b = 0; b < GT; b++)
+                    if ((alive >> b & 1) && twl<long long>(tw, GW_CLEAN + b) == 0) stopm |= 1u << b;
+                alive &= ~stopm;
+                early_m |= stopm & (uint32_t)twl<ull>(tw, GW_KEPTM);   // stopped with far entries left
+            }
+            const bool done = nkeep == 0 || alive == 0;
+            const int64_t Tn = done ? 0 : (twl<int64_t>(tw, GW_MINP) / delta + 1) * delta;
+            if (!team_sync(tw, W, nb, S, p.err)) return;   // everyone has read the results
+            if (done) break;
+            if (leader) {
+                tws(tw, GW_FARL, 0); tws(tw, GW_FAR2L, 0); tws(tw, GW_MINP, INF); tws(tw, GW_TB, Tn); tws(tw, GW_KEPTM, 0);
+                for (int b = 0; b < GT; b++) { tws(tw, GW_CLEAN + b, 0); tws(tw, GW_FCLEAN + b, 0); }
+            }
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+            // ---- next bucket: each kept (vertex, tree) goes to the near list of
+            //      this round when its distance is below the new bound, else
+            //      back to the far list
+            if (tid < GT) S.lfcl[tid] = 0;
+            __syncthreads();
+            for (int64_t i = tgtid; i < nkeep; i += tthreads) {
+                const int32_t v = lget<SC>(&far2[i], n);
+                const uint32_t fm = ld<SC>(&fmask[v]);
+                uint32_t m = fm & GBITS & alive, tonear = 0, tofar = 0;
+                while (m) {
+                    const int b = __ffs(m) - 1;
+                    m &= m - 1;
+                    const K kv = ld<SC>(&key[(int64_t)v * GT + b]);
+                    if ((int64_t)(kv >> 1) < Tn) {
+                        tonear |= 1u << b;
+                    } else {
+                        tofar |= 1u << b;
+                        if (kv & 1) atomicAdd(&S.lfcl[b], 1u);
+                    }
+                }
+                bool pn = false, pf = false;
+                if (tonear) {
+                    aand<SC>(&fmask[v], ~tonear);
+                    const uint32_t o = __hip_atomic_fetch_or(&mask[v], tonear << sh, __ATOMIC_RELAXED, SC);
+                    pn = ((o >> sh) & GBITS) == 0;
+                }
+                if (tofar) {
+                    const uint32_t o = aor<SC>(&fmask[v], GF_FAR_IN);
+                    pf = (o & GF_FAR_IN) == 0;
+                }
+                int64_t q = wave_append(pn, (ull*)&tw[GW_CNT0 + it % 3]);
+                if (pn && q < n) lput<SC>(&cur[q], v);
+                q = wave_append(pf, (ull*)&tw[GW_FARL]);
+                if (pf && q < n) lput<SC>(&far[q], v);
+            }
+            __syncthreads();
+            if (tid < GT && S.lfcl[tid]) atomicAdd((ull*)&tw[GW_FCLEAN + tid], (ull)S.lfcl[tid]);
+            if (!team_sync(tw, W, nb, S, p.err)) return;
+        }
+        // ---- labels: a touched vertex v gets (v, h_b, d) for every tree b of
+        //      the group whose key of v is reached and clean
+        const int64_t nt = min(twl<int64_t>(tw, GW_TOUCHEDL), (int64_t)n);
+        if (tid < GT) S.lnl[tid] = 0;
+        __syncthreads();
+        for (int64_t i = tgtid; i < nt; i += tthreads) {
+            const int32_t v = lget<SC>(&touched[i], n);
+            for (int b = 0; b < GT; b++) {
+                if (!(valid >> b & 1)) continue;
+                const K kv = ld<SC>(&key[(int64_t)v * GT + b]);
+                if (kv != KeyTraits<K>::INF && (kv & 1)) atomicAdd(&S.lnl[b], 1ull);
+            }
+        }
+        __syncthreads();
+        if (tid < GT && S.lnl[tid]) {
+            atomicAdd((ull*)&tw[GW_NLABB + tid], S.lnl[tid]);
+            atomicAdd((ull*)&tw[GW_NLABT], S.lnl[tid]);
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        if (leader) {
+            const ull nl = twl<ull>(tw, GW_NLABT);
+            const ull b0 = atomicAdd(p.pool.cursor, nl);
+            if (b0 + nl > p.pool.cap) {
+                tws(tw, GW_BASEP, -1);
+                atomicOr(p.err, ERR_BIT_POOL);
+                atomicExch(p.stop, 1);
+                atomicMin(p.pool.fail_base, b0);
+                for (int b = 0; b < GT; b++)
+                    if (valid >> b & 1) p.failed[atomicAdd(p.nfailed, 1)] = twl<int32_t>(tw, GW_ROOT + b);
+            } else {
+                tws(tw, GW_BASEP, (long long)b0);
+            }
+        }
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+        const long long pbase = twl<long long>(tw, GW_BASEP);
+        const long long nl = twl<long long>(tw, GW_NLABT);
+        bool ovf = false;
+        for (int64_t i = tgtid; i < nt; i += tthreads) {
+            const int32_t v = lget<SC>(&touched[i], n);
+            for (int b = 0; b < GT; b++) {
+                K kv = KeyTraits<K>::INF;
+                if (valid >> b & 1) {
+                    kv = ld<SC>(&key[(int64_t)v * GT + b]);
+                    st<SC>(&key[(int64_t)v * GT + b], KeyTraits<K>::INF);
+                }
+                const bool lab = kv != KeyTraits<K>::INF && (kv & 1);
+                const uint64_t d = (uint64_t)(kv >> 1);
+                const int64_t q = wave_append(lab, (ull*)&tw[GW_FILLP]);
+                if (lab && pbase >= 0 && q < nl) {
+                    ovf |= d > 0x7FFFFFFEull;
+                    p.pool.v[pbase + q] = v;
+                    p.pool.hub[pbase + q] = S.hroot[b];
+                    p.pool.dist[pbase + q] = (int32_t)d;
+                }
+            }
+            st<SC>(&mask[v], 0u);
+            st<SC>(&fmask[v], 0u);
+        }
+        if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
+        if (p.stats && leader) {
+            const int64_t ticks = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
+            for (int b = 0; b < GT; b++) {
+                if (!(valid >> b & 1)) continue;
+                int64_t* s = p.stats + (int64_t)S.hroot[b] * STAT_COLS;
+                s[0] = twl<long long>(tw, GW_SETTLEDB + b); s[1] = twl<long long>(tw, GW_ARCSB + b);
+                s[2] = twl<long long>(tw, GW_NLABB + b); s[3] = (early_m >> b) & 1;
+                s[4] = it; s[5] = ticks;
+            }
+        }
+        // the group is done in every workgroup before the leader resets the words
+        if (!team_sync(tw, W, nb, S, p.err)) return;
+    }
+}
+
 template <typename K, int WG>
 int launch_batched_t(const TreeParams& p, int phase, hipStream_t st) {
     const bool pr = p.poff != nullptr && p.pbound > 0;
@@ -1053,6 +1579,29 @@ int launch_team_t(const TreeParams& p, int W, int nteams, long long* tstate, int
     const void* f = pr ? (const void*)k_tree_team<K, WG, true> : (const void*)k_tree_team<K, WG, false>;
     hipError_t e = hipLaunchCooperativeKernel(f, dim3(nteams * W), dim3(WG), args, dl, st);
     return e == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int launch_group_t(const TreeParams& p, int W, int ngroups, long long* gstate, int32_t* far2, uint32_t* gmask,
+                   hipStream_t st) {
+    TreeParams pp = p;
+    const bool pr = p.poff != nullptr && p.pbound > 0;
+    const size_t dl = pr ? (size_t)GT * p.pbound * 4 : 0;
+    void* args[] = {(void*)&pp, (void*)&W, (void*)&gstate, (void*)&far2, (void*)&gmask};
+    const void* f = pr ? (const void*)k_tree_group<K, WG, true> : (const void*)k_tree_group<K, WG, false>;
+    hipError_t e = hipLaunchCooperativeKernel(f, dim3(ngroups * W), dim3(WG), args, dl, st);
+    return e == hipSuccess ? 0 : -1;
+}
+
+template <typename K, int WG>
+int group_capacity_t(int pbound) {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tree_group<K, WG, true>, WG, (size_t)GT * pbound * 4) !=
+        hipSuccess)
+        return 0;
+    return per * cus;
 }
 
 template <typename K, int WG>
@@ -1125,6 +1674,17 @@ int launch_tree_team(const TreeParams& p, int key_bits, int wg, int team_size, i
         if (wg == 1024) return launch_team_t<uint64_t, 1024>(p, team_size, nteams, tstate, far2, st);
     }
     return -1;
+}
+
+int launch_tree_group(const TreeParams& p, int key_bits, int wg, int team_size, int ngroups, long long* gstate,
+                      int32_t* far2, uint32_t* gmask, hipStream_t st) {
+    if (team_size < 1 || ngroups < 1 || wg != 1024) return -1;
+    if (key_bits == 32) return launch_group_t<uint32_t, 1024>(p, team_size, ngroups, gstate, far2, gmask, st);
+    return launch_group_t<uint64_t, 1024>(p, team_size, ngroups, gstate, far2, gmask, st);
+}
+
+int group_capacity(int key_bits, int pbound) {
+    return key_bits == 32 ? group_capacity_t<uint32_t, 1024>(pbound) : group_capacity_t<uint64_t, 1024>(pbound);
 }
 
 int team_capacity(int key_bits, int wg) {

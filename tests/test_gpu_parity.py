@@ -59,9 +59,36 @@ def test_random_small(seed):
                dict(mode="batched", delta=1000, wg_size=512, autotune=False, prune_hubs=-1),
                dict(mode="batched", delta=3, wg_size=1024, autotune=False, prune_hubs=4 * (1 + seed % 16)),
                dict(mode="batched", delta=2 + seed % 5, autotune=False, team_wgs=2 + seed % 15),
+               dict(mode="batched", delta=1 + seed % 5, autotune=False, team_wgs=2 + seed % 15, groups=False),
                dict(mode="plain", delta=2, autotune=False)):
         L, off, hub, dist = gpu_labels(row, col, w, order, **kw)
         assert_same_labels(off, hub, dist, ref, str(kw))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_groups_random(seed):
+    """Levels grown as groups of 16 trees with vertex-major keys, on random
+    multigraphs with few distinct weights (many ties) and random or degree
+    ranks: a prefix of up to 1024 hubs puts 112 trees in the level [16, 128),
+    which runs as 7 groups (with early termination and without, and with
+    ragged group counts from odd prefix sizes)."""
+    g = np.random.default_rng(100 + seed)
+    n = int(g.integers(300, 2500))
+    m = int(g.integers(n, 4 * n))
+    wmax = int(g.integers(1, 8))
+    e = [(int(a), int(b), int(c)) for a, b, c in
+         zip(g.integers(0, n, m), g.integers(0, n, m), g.integers(1, wmax + 1, m))]
+    row, col, w = pins.csr_from_edges(n, e)
+    order = gg.random_rank(n, seed) if seed % 2 else gg.degree_rank(row, seed)
+    ref = oracle.chl(row, col, w, order)
+    for kw in (dict(prune_hubs=min(1024, n // 2), autotune=False, delta=1 + seed % 3),
+               dict(prune_hubs=min(500, n // 2), autotune=False, early_term=False, delta=2)):
+        _say("groups random", seed, n, m, wmax, kw)
+        L, off, hub, dist = gpu_labels(row, col, w, order, **kw)
+        st = L.stats(per_root=True)
+        assert any(t < 0 for t in st["level_teams"]), st["level_teams"]
+        assert_same_labels(off, hub, dist, ref, str(kw))
+        assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
 
 
 def test_grid64_full():
@@ -98,19 +125,25 @@ def test_parameter_invariance_rmat12(k, wg, delta, eta, team):
 
 
 @pytest.mark.parametrize("team", [1, 2, 3, 8, 16])
-def test_team_sizes_rmat14(team):
-    """The first levels grown by teams of 1..16 workgroups per tree: same
-    labels and the same labels per root as the oracle; with early
-    termination off as well."""
+@pytest.mark.parametrize("groups", [False, True])
+def test_team_sizes_rmat14(team, groups):
+    """The first levels grown by teams of 1..16 workgroups per tree, or as
+    groups of 16 trees per team (vertex-major keys): same labels and the same
+    labels per root as the oracle; with early termination off as well."""
     c = gg.make_config("rmat14s11")
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
     for early in (True, False):
-        _say("teams", team, early)
+        _say("teams", team, "groups", groups, early)
         L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], team_wgs=team,
-                                       early_term=early, autotune=False, prune_hubs=1024)
+                                       early_term=early, autotune=False, prune_hubs=1024, groups=groups)
         assert_same_labels(off, hub, dist, ref)
         st = L.stats(per_root=True)
         assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+        lt = st["level_teams"]
+        if groups and team != 1:
+            assert lt[1] < 0, lt                    # [16,128): 112 trees as groups of 16
+        else:
+            assert all(t > 0 for t in lt), lt
 
 
 def test_team_grid():
@@ -121,6 +154,7 @@ def test_team_grid():
     c = gg.make_config("grid128x128_5")
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
     for kw in (dict(team_wgs=4), dict(team_wgs=16, prune_hubs=256, autotune=False),
+               dict(team_wgs=4, prune_hubs=256, autotune=False, groups=False),
                dict(prune_hubs=1024, wg_size=256, autotune=False)):
         _say("team grid", kw)
         L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], **kw)

@@ -67,7 +67,8 @@ def _digest_check(L, want, where):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("name,kw", [("rmat20", {}), ("rmat20", {"team_wgs": 2}), ("grid1024d", {})],
+@pytest.mark.parametrize("name,kw", [("rmat20", {}), ("rmat20", {"team_wgs": 2, "groups": False}),
+                                     ("grid1024d", {})],
                          ids=["rmat20", "rmat20-team2", "grid1024d"])
 def test_full_build_digests(name, kw):
     """The complete default build (validation, renumbering, every pruning
@@ -84,7 +85,10 @@ def test_full_build_digests(name, kw):
     assert st["labels"] == want["total"]
     if name == "rmat20":
         assert st["levels"] >= 2 and st["prune_hubs"] > 0
-        assert any(t > 1 for t in st["level_teams"])
+        if kw.get("groups", True):
+            assert any(t < 0 for t in st["level_teams"]), st["level_teams"]     # groups of 16 trees
+        else:
+            assert any(t > 1 for t in st["level_teams"]), st["level_teams"]     # teams
     _digest_check(L, want, name)
     L.free()
 
@@ -99,26 +103,31 @@ def _ref(name):
     return _REF[name]
 
 
-@pytest.mark.parametrize("team,prune", [(0, 0), (2, 0), (16, 1024), (1, 1024)])
-def test_u64_keys_levels_rmat14(team, prune):
+@pytest.mark.parametrize("team,prune,groups", [(0, 0, True), (2, 0, False), (16, 1024, False), (1, 1024, True),
+                                              (0, 1024, True)])
+def test_u64_keys_levels_rmat14(team, prune, groups):
     """R-MAT 14 with weights up to 2^18: (n - 1) * w_max >= 2^31, so the
     build takes 64-bit keys through the team levels, the wide levels (more
     trees than team slots: a 1024-hub prefix has the level [128, 1024)) and
     the main phase (all pruned but the first level); labels and labels per
     root equal the oracle's."""
     c, ref = _ref("rmat14s11w18")
-    _say("u64 rmat14", team, prune)
-    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], team_wgs=team, prune_hubs=prune)
+    _say("u64 rmat14", team, prune, groups)
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], team_wgs=team, prune_hubs=prune,
+                                   groups=groups)
     st = L.stats(per_root=True)
     _say("levels", st["level_end"], "teams", st["level_teams"], "prune", st["prune_hubs"])
+    lt = st["level_teams"]
     assert st["key_bits"] == 64
     assert st["levels"] >= 3 and st["prune_hubs"] > 0
-    if team != 1:
-        assert any(t > 1 for t in st["level_teams"]), "no team launch"
+    if team == 1:
+        assert all(t == 1 for t in lt)
+    elif groups:
+        assert any(t < 0 for t in lt), "no group launch"
     else:
-        assert all(t == 1 for t in st["level_teams"])
-    if prune == 1024:
-        assert any(t == 1 for t in st["level_teams"][1:]), "no wide (batched) pruned level"
+        assert any(t > 1 for t in lt), "no team launch"
+    if prune == 1024 and not groups:
+        assert any(t == 1 for t in lt[1:]), "no wide (batched) pruned level"
     assert_same_labels(off, hub, dist, ref, "u64 team=%d" % team)
     assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
     q = L.query(c["pairs"]).cpu().numpy()
