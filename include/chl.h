@@ -147,6 +147,14 @@ typedef struct chl_build_opts {
                                 vertex's keys of all 16 trees); -1: each tree
                                 alone (teams or one workgroup). Ignored when
                                 team_wgs is 1. Same labels either way. */
+    int32_t small_trees;     /* batched form, main phase: 1: one 64-thread
+                                workgroup per tree with the tree's state in
+                                LDS (at most 128 vertices reached and 256
+                                prefix labels of the root; the trees that
+                                need more are grown by the batched kernel
+                                afterwards); -1: the batched kernel alone;
+                                0: chosen by the autotuner (off when autotune
+                                is 0). Same labels either way. */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */
@@ -328,6 +336,8 @@ typedef struct chl_stats {
     int64_t level_teams[CHL_MAX_LEVELS];  /* workgroups per tree of the level (1: batched
                                              kernel); -w: groups of 16 trees, w
                                              workgroups per group */
+    int64_t small_trees;     /* workgroups of the small-tree kernel in the main
+                                phase (0: not used) */
 } chl_stats;
 
 /* Totals into *totals (host, may be NULL). per_root (may be NULL) receives

@@ -155,6 +155,7 @@ struct TuneKey {
 struct TuneVal {
     int k, wg;          // trees in flight, workgroup size
     int64_t delta;      // bucket width
+    bool small = false; // main phase by the small-tree kernel (LDS), the others as fallback
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -338,8 +339,9 @@ void free_groups(Arena& A, GroupCfg& gc) {
 int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int early,
                 const int32_t* roots_host, int32_t nroots, hipStream_t st, int* launches,
                 int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr,
-                bool roots_in_place = false, const GroupCfg* grp = nullptr) {
+                bool roots_in_place = false, const GroupCfg* grp = nullptr, int small_wgs = 0) {
     std::vector<int32_t> pending;
+    std::vector<int32_t> overflow;      // roots the small kernel gave up (grown afterwards)
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
         HIPCHK(hipMemcpyAsync(B.roots, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, st));
@@ -349,8 +351,10 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
     }
     for (;;) {
         HIPCHK(hipMemsetAsync(B.ctl32, 0, 12, st));          // next_root, stop, nfailed
+        HIPCHK(hipMemsetAsync(B.ctl32 + 5, 0, 4, st));       // overflow count of the small kernel
         HIPCHK(hipMemsetAsync(B.ctl64 + 1, 0xFF, 8, st));     // fail_base = none
         TreeParams p = params(B, grp ? grp->s : s, delta, early, dev_roots, nroots, root_base);
+        if (small_wgs) p.pop_batch = std::max(1, std::min(16, nroots / std::max(1, 8 * small_wgs)));
         HostCtl* hc = host_ctl();
         if (!hc) return CHL_ERR_HIP;
         if (team) HIPCHK(hipMemsetAsync(team->tstate, 0, (size_t)team->nteams * TEAM_WORDS * 8, st));
@@ -359,7 +363,9 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
             // the launch is timed by events; the control words are read back
             // behind it, and one synchronisation completes both
             Timer tk(st);
-            if (grp) {
+            if (small_wgs) {
+                if (launch_tree_small(p, B.key_bits, small_wgs, B.far2, B.ctl32 + 5, st)) return CHL_ERR_HIP;
+            } else if (grp) {
                 if (launch_tree_group(p, B.key_bits, 1024, grp->size, grp->ngroups, grp->gstate, grp->far2,
                                       grp->gmask, st))
                     return CHL_ERR_HIP;
@@ -370,20 +376,25 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
                 return CHL_ERR_HIP;
             }
             tk.record_end();
-            HIPCHK(hipMemcpyAsync(hc->c32, B.ctl32, 16, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(hc->c32, B.ctl32, 24, hipMemcpyDeviceToHost, st));
             HIPCHK(hipMemcpyAsync(hc->c64, B.ctl64, 16, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             const double ms = tk.elapsed();
             if (phase != 1) { B.kernel_ms += ms; B.kernel_launches++; }
         }
         (*launches)++;
-        int32_t c32[4];
+        int32_t c32[6];
         unsigned long long c64[2];
         std::memcpy(c32, hc->c32, sizeof(c32));
         std::memcpy(c64, hc->c64, sizeof(c64));
         B.last_used = c64[0];
         if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
         if (c32[3] & ERR_BIT_TEAM) return CHL_ERR_HIP;
+        if (small_wgs && c32[5] > 0) {
+            const size_t no = overflow.size();
+            overflow.resize(no + (size_t)std::min(c32[5], B.n));
+            HIPCHK(hipMemcpy(overflow.data() + no, B.far2, (overflow.size() - no) * 4, hipMemcpyDeviceToHost));
+        }
         if (!(c32[3] & ERR_BIT_POOL)) break;
         // pool full: keep what fitted, then resume with the failed roots and
         // the roots the queue had not handed out yet
@@ -420,6 +431,10 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         HIPCHK(hipStreamSynchronize(st));
         dev_roots = B.roots;
         if (nroots == 0) break;
+    }
+    if (!overflow.empty()) {
+        std::sort(overflow.begin(), overflow.end());   // rank order
+        return run_batched(A, B, s, wg, delta, early, overflow.data(), (int32_t)overflow.size(), st, launches, phase);
     }
     return 0;
 }
@@ -643,7 +658,7 @@ void chl_labels_free(chl_labels* h) {
 
 // ====================================================================== build
 static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_opts& o,
-                       hipStream_t st, int& k, int& wg, int64_t& delta, double& tune_ms);
+                       hipStream_t st, int& k, int& wg, int64_t& delta, bool& small, double& tune_ms);
 
 // The rank-prefix levels of a batched build (see chl_build_impl): grows the
 // trees of the roots [0, grown) and leaves their labels in the pool, the
@@ -898,6 +913,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.prune_hubs > MAX_PREFIX) return CHL_ERR_INVALID_ARG;
     if (o.team_wgs < 0 || o.team_wgs > 16) return CHL_ERR_INVALID_ARG;
     if (o.group_levels < -1 || o.group_levels > 0) return CHL_ERR_INVALID_ARG;
+    if (o.small_trees < -1 || o.small_trees > 1) return CHL_ERR_INVALID_ARG;
     if (o.root_count > 0) {
         if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
         if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;
@@ -1013,7 +1029,9 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     int k = 0, wg = 0;
     int64_t delta = 0;
     double tune_ms = 0;
-    if (int r = pick_params(A, B, g, o, st, k, wg, delta, tune_ms)) return r;
+    bool small = false;
+    if (int r = pick_params(A, B, g, o, st, k, wg, delta, small, tune_ms)) return r;
+    S.small_trees = small ? small_capacity(B.key_bits) : 0;
     S.tune_ms = tune_ms;
     S.roots_in_flight = k;
     S.wg_size = wg;
@@ -1039,7 +1057,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
                 ? run_plain(A, B, s, wg, delta, o.early_term, sel, st, &launches)
                 : run_batched(A, B, s, wg, delta, o.early_term, sel.empty() ? nullptr : sel.data(),
                               sel.empty() ? n - grown : (int32_t)sel.size(), st, &launches, 0,
-                              sel.empty() ? grown : 0);
+                              sel.empty() ? grown : 0, nullptr, false, nullptr, (int)S.small_trees);
     if (r) return r;
     S.tree_ms = ttree.stop();
     if (tp) prune_ms = tp->elapsed();
@@ -1113,7 +1131,7 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
 
 // ---------------------------------------------------------------- tuner
 static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_opts& o, hipStream_t st,
-                       int& k, int& wg, int64_t& delta, double& tune_ms) {
+                       int& k, int& wg, int64_t& delta, bool& small, double& tune_ms) {
     const int32_t n = B.n;
     const double wmean = 0.5 * (1.0 + B.maxw);
     size_t freeb = 0, totalb = 0;
@@ -1123,12 +1141,14 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     k = o.roots_in_flight ? std::min(o.roots_in_flight, kmax) : std::min(kmax, 1024);
     wg = o.wg_size ? o.wg_size : 256;
     delta = o.delta ? o.delta : std::max<int64_t>(1, (int64_t)(wmean));
+    small = o.small_trees > 0;
     if (o.mode == CHL_MODE_PLAIN) {
+        small = false;
         if (!o.wg_size) wg = 256;
         if (!o.delta) delta = std::max<int64_t>(1, (int64_t)(4 * wmean));
         return 0;
     }
-    bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta);
+    bool need = o.autotune && (!o.roots_in_flight || !o.wg_size || !o.delta || o.small_trees == 0);
     if (!need) return 0;
     // (unpruned builds share one entry whether or not their first roots ran
     // as a level)
@@ -1140,6 +1160,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             if (!o.roots_in_flight) k = std::min(it->second.k, kmax);
             if (!o.wg_size) wg = it->second.wg;
             if (!o.delta) delta = it->second.delta;
+            if (!o.small_trees) small = it->second.small;
             return 0;
         }
     }
@@ -1243,6 +1264,27 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
             if (rank[i].first + ms < best2) { best2 = rank[i].first + ms; bv = TuneVal{kk, w, d}; }
         }
     }
+    // then the small-tree kernel (trees in LDS, the batched kernel with the
+    // setting found for the trees that do not fit), against the best setting
+    if (!o.small_trees && small_capacity(B.key_bits) > 0) {
+        const int kk = std::max(1, std::min(bv.k, kmax));
+        double ms_b = 0, ms_s = 0;
+        if (int r = time_once(kk, bv.wg, bv.delta, ms_b)) return r;
+        if (kk != kcur) {
+            free_slots(A, s);
+            if (int r = alloc_slots(A, B, kk, s, st)) return r;
+            kcur = kk;
+        }
+        HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
+        {
+            Timer t(st);
+            if (int r = run_batched(A, B, s, bv.wg, bv.delta, o.early_term, probe.data(), (int32_t)probe.size(), st,
+                                    &launches, 1, 0, nullptr, false, nullptr, small_capacity(B.key_bits)))
+                return r;
+            ms_s = t.stop();
+        }
+        bv.small = ms_s < ms_b;
+    }
     free_slots(A, s);
     B.stats = saved_stats;
     HIPCHK(hipMemcpyAsync(B.ctl64, &B.cursor_base, 8, hipMemcpyHostToDevice, st));
@@ -1251,6 +1293,7 @@ static int pick_params(Arena& A, Build& B, const chl_graph* g, const chl_build_o
     k = bv.k;
     wg = bv.wg;
     delta = bv.delta;
+    if (!o.small_trees) small = bv.small;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = bv;
     return 0;

@@ -160,6 +160,12 @@ int team_capacity(int key_bits, int wg);   // co-resident workgroups of the team
 // i * 2n: two mask words per vertex, zero between groups; gstate GROUP_WORDS
 // words per team, zeroed before the launch). Cooperative launch; pbound <=
 // GROUP_MAX_PREFIX.
+// Small trees: one 64-thread workgroup per tree, its state in LDS (at most
+// 128 vertices, at most 256 prefix labels of its root); roots of trees that
+// do not fit are appended to ovf (count *novf, zeroed by the caller) without
+// emitting anything. Same root queue, pool and statistics as the batched form.
+int launch_tree_small(const TreeParams& p, int key_bits, int nwg, int32_t* ovf, int32_t* novf, hipStream_t st);
+int small_capacity(int key_bits);   // co-resident workgroups of the small kernel
 constexpr int GROUP_TREES = 16;
 constexpr int GROUP_WORDS = 256;
 constexpr int GROUP_MAX_PREFIX = 1024;

@@ -1020,6 +1020,418 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
     }
 }
 
+// ---------------------------------------------------------------- small
+// One wave per tree, its whole state in LDS: a hash table of at most SCAP
+// vertices (vertex id, packed key, list flags) and the near and far lists as
+// table slots. Most trees of the main phase settle a few vertices, and a tree
+// then needs a few kilobytes instead of an n-sized slot, so that 32 trees fit
+// on a compute unit and their key accesses stay on chip. The root's
+// distances to the prefix hubs (rank-prefix pruning) sit in a second small
+// hash table. A tree that needs more room than either table holds is given
+// up without emitting anything and its root appended to an overflow list,
+// which the host runs with the batched kernel afterwards (trees are
+// independent, Section 4.2). Rounds, buckets, early termination and label
+// emission follow the batched form step for step, with table slots in place
+// of vertex ids.
+constexpr int SCAP = 128;            // vertices a tree may reach in LDS
+constexpr int SPH = 512;             // prefix-label table of a root (at most SPH / 2 labels)
+constexpr int32_t S_EMPTY = -1;
+
+template <typename K>
+struct SmallLds {
+    int32_t ids[SCAP];
+    K keys[SCAP];
+    uint32_t flg[SCAP];              // bit 0/1: in near list 0/1, bit 2: in far list
+    uint16_t lst[3][SCAP];           // near list 0, near list 1, far list (slots)
+    int32_t phub[SPH];               // root's prefix labels: hub (S_EMPTY: free)
+    uint32_t pdist[SPH];             //                       distance
+    int64_t beg[64];                 // relaxation of up to 64 list entries
+    uint32_t off[64];
+    K ekey[64];
+    int32_t esl[64];
+    uint32_t wsum[1];
+    unsigned long long red64[1];
+    int32_t red32[1];
+    int32_t ncur, cnt_next, cnt_far, nkeep, far_clean, nused, bad, fill;
+    int32_t root, bnext, bend;
+    unsigned long long umax;
+    long long pool_base;
+};
+
+__device__ __forceinline__ uint32_t shash(uint32_t x, uint32_t cap) {
+    return (x * 2654435761u) >> (32 - __builtin_ctz(cap));
+}
+
+// slot of u in the table, or -1
+template <typename K>
+__device__ __forceinline__ int slookup(SmallLds<K>& S, int32_t u) {
+    uint32_t s = shash((uint32_t)u, SCAP);
+    for (int i = 0; i < SCAP; i++, s = (s + 1) & (SCAP - 1)) {
+        const int32_t x = __hip_atomic_load(&S.ids[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (x == u) return (int)s;
+        if (x == S_EMPTY) return -1;
+    }
+    return -1;
+}
+
+// slot of u, inserted if absent (its key is then INF); -1 when the table is full
+template <typename K>
+__device__ __forceinline__ int sinsert(SmallLds<K>& S, int32_t u) {
+    uint32_t s = shash((uint32_t)u, SCAP);
+    for (int i = 0; i < SCAP; i++, s = (s + 1) & (SCAP - 1)) {
+        const int32_t x = atomicCAS(&S.ids[s], S_EMPTY, u);
+        if (x == S_EMPTY) { atomicAdd(&S.nused, 1); return (int)s; }
+        if (x == u) return (int)s;
+    }
+    return -1;
+}
+
+// the root's distance to prefix hub x (0xFFFFFFFF: none)
+template <typename K>
+__device__ __forceinline__ uint32_t sprefix(const SmallLds<K>& S, uint32_t x) {
+    uint32_t s = shash(x, SPH);
+    for (int i = 0; i < SPH; i++, s = (s + 1) & (SPH - 1)) {
+        const int32_t y = S.phub[s];
+        if (y == (int32_t)x) return S.pdist[s];
+        if (y == S_EMPTY) return 0xFFFFFFFFu;
+    }
+    return 0xFFFFFFFFu;
+}
+
+// One round over the list entries cur[base .. base + nv), nv <= 64: the
+// batched form's relaxation with table slots. An arc to a vertex that is not
+// in the table (and not pruned) inserts it; a full table marks the tree bad.
+template <typename K, bool PRUNE>
+__device__ __forceinline__ void srelax(const TreeParams& p, SmallLds<K>& S, const uint16_t* cur, int32_t base,
+                                       int32_t nv, uint32_t curbit, uint32_t nextbit, int32_t h, int64_t T,
+                                       uint16_t* next, uint16_t* far, uint64_t& arcs) {
+    constexpr int SCW = __HIP_MEMORY_SCOPE_WORKGROUP;
+    const int lane = threadIdx.x;
+    uint32_t deg = 0;
+    if (lane < nv) {
+        const int32_t s = cur[base + lane];
+        atomicAnd(&S.flg[s], ~curbit);
+        const int32_t v = S.ids[s];
+        const int64_t b = p.g.row[v];
+        deg = (uint32_t)(p.g.row[v + 1] - b);
+        S.beg[lane] = b;
+        S.ekey[lane] = S.keys[s];
+        S.esl[lane] = s;
+    }
+    uint32_t inc = deg;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    const uint32_t total = __shfl(inc, 63);
+    S.off[lane] = inc - deg;
+    __syncthreads();
+    arcs += total;
+    unsigned long long my_umax = 0;
+    for (uint32_t e0 = lane; e0 < total; e0 += 64 * RELAX_ILP) {
+        int own[RELAX_ILP];
+        uint64_t a[RELAX_ILP];
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * 64;
+            int lo = 0, hi = nv - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.off[mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            own[j] = lo;
+            a[j] = e < total ? p.g.arc[S.beg[lo] + (e - S.off[lo])] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < RELAX_ILP; j++) {
+            const uint32_t e = e0 + j * 64;
+            const bool valid = e < total;
+            const int32_t u = (int32_t)(a[j] >> 32);
+            const K kv = S.ekey[own[j]];
+            const uint64_t nd = (uint64_t)(kv >> 1) + (uint32_t)a[j];
+            const K nk = pack<K>(nd, (uint32_t)(kv & 1) & (uint32_t)(u > h));
+            int su = valid ? slookup(S, u) : -1;
+            const K seen = su >= 0 ? __hip_atomic_load(&S.keys[su], __ATOMIC_RELAXED, SCW) : KeyTraits<K>::INF;
+            bool cand = valid && nk < seen;
+            if (PRUNE && cand) {
+                // rank-prefix pruning (Section 4.3), as in the other forms,
+                // with the root's prefix distances from the LDS table
+                const int64_t lb = p.poff[u], le = p.poff[u + 1];
+                for (int64_t i = lb; i < le && cand; i += 4) {
+                    uint64_t lx[4];
+#pragma unroll
+                    for (int z = 0; z < 4; z++) lx[z] = i + z < le ? p.plab[i + z] : ~0ull;
+#pragma unroll
+                    for (int z = 0; z < 4; z++) {
+                        const uint32_t x = (uint32_t)(lx[z] >> 32);
+                        if (x >= (uint32_t)p.pbound) continue;
+                        const uint32_t ax = sprefix(S, x);
+                        if (ax != 0xFFFFFFFFu && (uint64_t)ax + (uint32_t)lx[z] <= nd) cand = false;
+                    }
+                }
+            }
+            if (cand && su < 0) {
+                su = sinsert(S, u);
+                if (su < 0) { S.bad = 1; cand = false; }
+            }
+            K old = seen;
+            if (cand) old = atomicMin(&S.keys[su], nk);
+            const bool imp = cand && nk < old;
+            const bool tonear = imp && (int64_t)nd < T;
+            bool pnear = false, pfar = false;
+            if (imp) {
+                if (nk & 1) my_umax = my_umax > nd ? my_umax : nd;
+                const uint32_t bit = tonear ? nextbit : FAR_BIT;
+                const uint32_t o = atomicOr(&S.flg[su], bit);
+                const bool fresh = (o & bit) == 0;
+                pnear = fresh && tonear;
+                pfar = fresh && !tonear;
+            }
+            int64_t q = wave_append(pnear, &S.cnt_next);
+            if (pnear && q < SCAP) next[q] = (uint16_t)su;
+            q = wave_append(pfar, &S.cnt_far);
+            if (pfar && q < SCAP) far[q] = (uint16_t)su;
+            (void)wave_append(pfar && (nk & 1), &S.far_clean);
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(my_umax, d);
+        my_umax = o > my_umax ? o : my_umax;
+    }
+    if (lane == 0 && my_umax > S.umax) S.umax = my_umax;
+    __syncthreads();
+}
+
+template <typename K, bool PRUNE>
+__global__ __launch_bounds__(64) void k_tree_small(TreeParams p, int32_t* ovf, int32_t* novf) {
+    __shared__ SmallLds<K> S;
+    const int lane = threadIdx.x;
+    const int64_t delta = p.delta;
+    for (int i = lane; i < SCAP; i += 64) {
+        S.ids[i] = S_EMPTY;
+        S.keys[i] = KeyTraits<K>::INF;
+        S.flg[i] = 0;
+    }
+    for (int i = lane; i < SPH; i += 64) S.phub[i] = S_EMPTY;
+    if (lane == 0) { S.bnext = 0; S.bend = 0; }
+    __syncthreads();
+    for (;;) {
+        if (lane == 0) {
+            // roots are taken pop_batch at a time, as in the batched form
+            int32_t r = -1;
+            const bool stopped = __hip_atomic_load(p.stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (stopped) {
+                for (int32_t c = S.bnext; c < S.bend; c++)
+                    p.failed[atomicAdd(p.nfailed, 1)] = p.roots ? p.roots[c] : p.root_base + c;
+                S.bnext = S.bend;
+            } else if (S.bnext >= S.bend) {
+                const int32_t c = atomicAdd(p.next_root, p.pop_batch);
+                S.bnext = c;
+                S.bend = c < p.nroots ? min(p.nroots, c + p.pop_batch) : c;
+            }
+            if (S.bnext < S.bend) {
+                r = p.roots ? p.roots[S.bnext] : p.root_base + S.bnext;
+                S.bnext++;
+            }
+            S.root = r;
+            S.ncur = 1; S.cnt_next = 0; S.cnt_far = 0; S.far_clean = 0; S.umax = 0; S.bad = 0; S.nused = 0;
+            S.fill = 0;
+        }
+        __syncthreads();
+        const int32_t h = S.root;
+        if (h < 0) break;
+        const bool prune = PRUNE && h >= p.pbound;
+        if (prune) {
+            // the root's prefix labels (a directed build reads the partner's)
+            const uint32_t px = (uint32_t)p.partner;
+            const int32_t hg = h ^ (int32_t)px;
+            const int64_t lb = p.poff[hg], le = p.poff[hg + 1];
+            if (le - lb > SPH / 2) {
+                if (lane == 0) S.bad = 1;       // (the table stays at most half full)
+            } else {
+                for (int64_t i = lb + lane; i < le; i += 64) {
+                    const uint64_t lx = p.plab[i];
+                    const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                    if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
+                        uint32_t s = shash(y, SPH);
+                        while (atomicCAS(&S.phub[s], S_EMPTY, (int32_t)y) != S_EMPTY) s = (s + 1) & (SPH - 1);
+                        S.pdist[s] = (uint32_t)lx;
+                    }
+                }
+            }
+        }
+        if (lane == 0) {
+            const int s = sinsert(S, h);
+            S.keys[s] = pack<K>(0, 1);
+            S.flg[s] = 1u;
+            S.lst[0][0] = (uint16_t)s;
+        }
+        __syncthreads();
+        int64_t T = delta;
+        int it = 0;
+        uint64_t arcs = 0, settled = 0;
+        const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+        bool early = false;
+        for (;;) {
+            if (S.bad) break;
+            bool stopped = false;
+            for (;;) {
+                const int32_t ncur = S.ncur;
+                const uint32_t curbit = 1u << (it & 1), nextbit = 1u << ((it + 1) & 1);
+                const uint16_t* cur = S.lst[it & 1];
+                uint16_t* next = S.lst[(it + 1) & 1];
+                if (p.early_term && it > 0 && S.far_clean == 0) {
+                    // the batched form's stop test over the current list
+                    unsigned long long mn = ~0ull;
+                    int32_t cl = 0;
+                    for (int32_t i = lane; i < ncur; i += 64) {
+                        const K kv = S.keys[cur[i]];
+                        mn = min(mn, (unsigned long long)(kv >> 1));
+                        cl |= (int32_t)(kv & 1);
+                    }
+#pragma unroll
+                    for (int d = 32; d >= 1; d >>= 1) {
+                        const unsigned long long o = __shfl_xor(mn, d);
+                        mn = o < mn ? o : mn;
+                        cl |= __shfl_xor(cl, d);
+                    }
+                    const unsigned long long lbd = mn < (unsigned long long)T ? mn : (unsigned long long)T;
+                    if (cl == 0 && lbd > S.umax) {
+                        for (int32_t i = lane; i < ncur; i += 64) atomicAnd(&S.flg[cur[i]], ~curbit);
+                        for (int32_t i = lane; i < S.cnt_far; i += 64) atomicAnd(&S.flg[S.lst[2][i]], ~FAR_BIT);
+                        early = ncur > 0 || S.cnt_far > 0;
+                        stopped = true;
+                        __syncthreads();
+                        break;
+                    }
+                }
+                settled += ncur;
+                for (int32_t base = 0; base < ncur; base += 64)
+                    srelax<K, PRUNE>(p, S, cur, base, min(64, ncur - base), curbit, nextbit, h, T, next, S.lst[2],
+                                     arcs);
+                it++;
+                if (lane == 0) { S.ncur = min(S.cnt_next, SCAP); S.cnt_next = 0; }
+                __syncthreads();
+                if (S.ncur == 0 || S.bad) break;
+            }
+            if (stopped || S.bad) break;
+            // bucket done: drop settled far entries, then move the next bucket in
+            const int32_t nfar = min(S.cnt_far, SCAP);
+            if (lane == 0) S.nkeep = 0;
+            __syncthreads();
+            unsigned long long mymin = ~0ull;
+            int32_t myclean = 0;
+            for (int32_t base = 0; base < nfar; base += 64) {
+                const int32_t i = base + lane;
+                bool keep = false;
+                int32_t s = 0;
+                K kv = 0;
+                if (i < nfar) {
+                    s = S.lst[2][i];
+                    atomicAnd(&S.flg[s], ~FAR_BIT);
+                    kv = S.keys[s];
+                    keep = (int64_t)(kv >> 1) >= T;
+                }
+                __syncthreads();
+                const int64_t q = wave_append(keep, &S.nkeep);
+                if (keep) {
+                    S.lst[2][q] = (uint16_t)s;
+                    mymin = min(mymin, (unsigned long long)(kv >> 1));
+                    myclean += (int32_t)(kv & 1);
+                }
+                __syncthreads();
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const unsigned long long o = __shfl_xor(mymin, d);
+                mymin = o < mymin ? o : mymin;
+                myclean += __shfl_xor(myclean, d);
+            }
+            const int32_t nk2 = S.nkeep;
+            if (nk2 == 0 || (p.early_term && myclean == 0)) { early = nk2 > 0; break; }
+            T = ((int64_t)mymin / delta + 1) * delta;
+            uint16_t* curl = S.lst[it & 1];
+            const uint32_t curbit = 1u << (it & 1);
+            if (lane == 0) { S.ncur = 0; S.cnt_far = 0; S.far_clean = 0; }
+            __syncthreads();
+            for (int32_t base = 0; base < nk2; base += 64) {
+                const int32_t i = base + lane;
+                int32_t s = 0;
+                bool tonear = false, tofar = false, fclean = false;
+                if (i < nk2) {
+                    s = S.lst[2][i];
+                    const K kv = S.keys[s];
+                    tonear = (int64_t)(kv >> 1) < T;
+                    tofar = !tonear;
+                    fclean = tofar && (kv & 1);
+                }
+                __syncthreads();
+                int64_t q = wave_append(tonear, &S.ncur);
+                if (tonear) { curl[q] = (uint16_t)s; atomicOr(&S.flg[s], curbit); }
+                q = wave_append(tofar, &S.cnt_far);
+                if (tofar) { S.lst[2][q] = (uint16_t)s; atomicOr(&S.flg[s], FAR_BIT); }
+                (void)wave_append(fclean, &S.far_clean);
+                __syncthreads();
+            }
+        }
+        if (S.bad) {
+            // the tree outgrew LDS: the batched kernel grows it later
+            if (lane == 0) ovf[atomicAdd(novf, 1)] = h;
+        } else {
+            // emit the labels of clean slots
+            int32_t mycnt = 0;
+            for (int i = lane; i < SCAP; i += 64)
+                mycnt += (S.ids[i] != S_EMPTY && (S.keys[i] & 1)) ? 1 : 0;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) mycnt += __shfl_xor(mycnt, d);
+            const int32_t nl = mycnt;
+            if (lane == 0) {
+                const unsigned long long b = atomicAdd(p.pool.cursor, (unsigned long long)nl);
+                if (b + (unsigned long long)nl > p.pool.cap) {
+                    S.pool_base = -1;
+                    atomicOr(p.err, ERR_BIT_POOL);
+                    atomicExch(p.stop, 1);
+                    atomicMin(p.pool.fail_base, b);
+                    p.failed[atomicAdd(p.nfailed, 1)] = h;
+                } else {
+                    S.pool_base = (long long)b;
+                }
+            }
+            __syncthreads();
+            const long long pb = S.pool_base;
+            bool ovfd = false;
+            for (int i = lane; i < SCAP; i += 64) {
+                const bool lab = S.ids[i] != S_EMPTY && (S.keys[i] & 1);
+                const uint64_t d = (uint64_t)(S.keys[i] >> 1);
+                const int64_t q = wave_append(lab, &S.fill);
+                if (lab && pb >= 0) {
+                    ovfd |= d > 0x7FFFFFFEull;
+                    p.pool.v[pb + q] = S.ids[i];
+                    p.pool.hub[pb + q] = h;
+                    p.pool.dist[pb + q] = (int32_t)d;
+                }
+            }
+            if (ovfd) atomicOr(p.err, ERR_BIT_OVERFLOW);
+            if (p.stats && lane == 0) {
+                int64_t* s = p.stats + (int64_t)h * STAT_COLS;
+                s[0] = (int64_t)settled; s[1] = (int64_t)arcs; s[2] = nl; s[3] = early ? 1 : 0;
+                s[4] = it; s[5] = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
+            }
+        }
+        __syncthreads();
+        // clear the tables for the next tree
+        for (int i = lane; i < SCAP; i += 64) {
+            S.ids[i] = S_EMPTY;
+            S.keys[i] = KeyTraits<K>::INF;
+            S.flg[i] = 0;
+        }
+        if (prune) for (int i = lane; i < SPH; i += 64) S.phub[i] = S_EMPTY;
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- groups
 // A team of W workgroups grows GT trees of consecutive roots together: the
 // trees of a pruning level whose roots are close in rank reach largely the
@@ -1581,6 +1993,23 @@ int launch_team_t(const TreeParams& p, int W, int nteams, long long* tstate, int
     return e == hipSuccess ? 0 : -1;
 }
 
+template <typename K>
+int launch_small_t(const TreeParams& p, int nwg, int32_t* ovf, int32_t* novf, hipStream_t st) {
+    const bool pr = p.poff != nullptr && p.pbound > 0;
+    if (pr) hipLaunchKernelGGL((k_tree_small<K, true>), dim3(nwg), dim3(64), 0, st, p, ovf, novf);
+    else hipLaunchKernelGGL((k_tree_small<K, false>), dim3(nwg), dim3(64), 0, st, p, ovf, novf);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <typename K>
+int small_capacity_t() {
+    int dev = 0, per = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_tree_small<K, true>, 64, 0) != hipSuccess) return 0;
+    return per * cus;
+}
+
 template <typename K, int WG>
 int launch_group_t(const TreeParams& p, int W, int ngroups, long long* gstate, int32_t* far2, uint32_t* gmask,
                    hipStream_t st) {
@@ -1681,6 +2110,15 @@ int launch_tree_group(const TreeParams& p, int key_bits, int wg, int team_size, 
     if (team_size < 1 || ngroups < 1 || wg != 1024) return -1;
     if (key_bits == 32) return launch_group_t<uint32_t, 1024>(p, team_size, ngroups, gstate, far2, gmask, st);
     return launch_group_t<uint64_t, 1024>(p, team_size, ngroups, gstate, far2, gmask, st);
+}
+
+int launch_tree_small(const TreeParams& p, int key_bits, int nwg, int32_t* ovf, int32_t* novf, hipStream_t st) {
+    if (nwg < 1) return -1;
+    return key_bits == 32 ? launch_small_t<uint32_t>(p, nwg, ovf, novf, st) : launch_small_t<uint64_t>(p, nwg, ovf, novf, st);
+}
+
+int small_capacity(int key_bits) {
+    return key_bits == 32 ? small_capacity_t<uint32_t>() : small_capacity_t<uint64_t>();
 }
 
 int group_capacity(int key_bits, int pbound) {

@@ -91,6 +91,36 @@ def test_groups_random(seed):
         assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
 
 
+@pytest.mark.parametrize("name,kw", [("rmat12s9", {}), ("rmat14s11", {"prune_hubs": 1024}),
+                                     ("rmat14s11w18", {}), ("grid64", {"prune_hubs": -1}),
+                                     ("grid128x128_5", {"prune_hubs": 256}), ("rmat10d3", {"directed": True})])
+def test_small_trees(name, kw):
+    """The main phase by the small-tree kernel (one wave per tree, its state
+    in LDS; trees that outgrow it grown again by the batched kernel): the
+    oracle's labels and labels per root, with and without early
+    termination (grids: most trees outgrow LDS and take the fallback)."""
+    c = gg.make_config(name)
+    directed = kw.pop("directed", False)
+    if directed:
+        ro, ri = oracle.chl_directed(c["row_ptr"], c["col"], c["w"], c["order"])
+    else:
+        ref = oracle.chl(c["row_ptr"], c["col"], c["w"], c["order"])
+    for early in (True, False):
+        _say("small trees", name, kw, early)
+        L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], c["order"], small=True, autotune=False,
+                                       early_term=early, directed=directed, **kw)
+        st = L.stats(per_root=not directed)
+        assert st["small_trees"] > 0
+        if directed:
+            assert_same_labels(off, hub, dist, ro, "out")
+            o2, h2, d2 = (t.numpy() for t in L.export_in("cpu"))
+            assert_same_labels(o2, h2, d2, ri, "in")
+        else:
+            assert_same_labels(off, hub, dist, ref, "%s %s" % (kw, early))
+            assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+        L.free()
+
+
 def test_grid64_full():
     """64x64 grid workload: full labeling, both forms, plus its 10^4 queries."""
     c = gg.make_config("grid64")
