@@ -231,7 +231,8 @@ def headline(chl, gg, counts, args, dev, stream):
     assert st["labels"] == units["labels"], "label count differs from the oracle's"
     gpu_arcs = int(st["per_root"][:, 1].sum())
     # roofline of the dominant kernels, the tree kernels (teams for the first
-    # levels, the batched kernel for the wide levels and the main phase):
+    # levels, tree groups for the levels of 64 to 256 roots, the batched kernel
+    # for the wider levels and the main phase):
     # every production launch of a build, timed with HIP events on the build
     # stream inside the library
     kms = float(np.median([k[0] for k in kern]))
@@ -247,8 +248,8 @@ def headline(chl, gg, counts, args, dev, stream):
             traffic = tr.get("hbm_bytes_per_launch")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "kernel": "tree kernels k_tree_team + k_tree_batched (every production launch of a build: team "
-                          "levels, wide levels, main phase)",
+                "kernel": "tree kernels k_tree_team + k_tree_group + k_tree_batched (every production launch of a "
+                          "build: team levels, group levels, wide levels, main phase)",
                 "kernel_ms": round(per_launch_ms, 3), "launches_per_build": nl, "alg_bytes_per_launch": ab,
                 "units_per_build": units}
     qps = pairs.shape[0] / (float(np.median(query_ms)) / 1e3)
@@ -577,6 +578,13 @@ def main():
     counts = json.load(open(COUNTS))
     stream = torch.cuda.current_stream()
     WORKLOAD = args.headline
+    chl.load()
+    # where the library is mapped (stack addresses in a profiler's or a
+    # crash report can then be attributed to it)
+    with open("/proc/self/maps") as f:
+        segs = [l.split()[0] for l in f if l.rstrip().endswith("libchl.so")]
+    if segs:
+        say("libchl.so mapped at %s-%s" % (segs[0].split("-")[0], segs[-1].split("-")[1]))
 
     say("headline: %s, %d warmup + %d steps" % (WORKLOAD, args.warmup, args.steps))
     H = headline(chl, gg, counts, args, dev, stream)
