@@ -42,7 +42,7 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic_tree_%s.json")
 # the tree kernels and the host code that picks their launches: byte counters
 # taken for other sources no longer describe the kernels
 TREE_SRC = [os.path.join(ROOT, "paper_1907_00140_amd", "csrc", f) for f in ("tree.hip", "api.cpp")]
-SECTIONS = ("headline", "workloads", "serving", "directed", "paths", "atomics", "cpu")
+SECTIONS = ("headline", "workloads", "serving", "directed", "hybrid", "paths", "atomics", "cpu")
 NAMES = {
     "grid64": "64x64 grid (4,096 vertices, 8,064 edges), int32 weights [1,100], degree rank",
     "rmat16": "R-MAT scale 16 (65,536 vertices, %d edges), int32 weights [1,1000], degree rank",
@@ -164,18 +164,30 @@ def queries_per_s(L, pairs, stream, reps=3):
 
 def plain_form(chl, d, n, head, strata, stream, full=False):
     """The plain one-root-per-launch form (the whole device grows one tree per
-    cooperative launch, unpruned): measured outright when `full`, else the
-    `head` first roots plus `strata` rank-stratified roots, the rest
-    extrapolated as sample time * stride."""
+    cooperative launch, unpruned): measured outright when `full` (every root
+    grown, in 8 consecutive root ranges so that each range reports when it
+    ends; the time is the sum of the 8 builds, their labels add up to the
+    complete labeling's), else the `head` first roots plus `strata`
+    rank-stratified roots, the rest extrapolated as sample time * stride."""
     import torch
     if full:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        Lp = chl.build(*d, mode="plain", stream=stream)
-        torch.cuda.synchronize()
-        s = time.perf_counter() - t1
-        Lp.free()
-        return {"build_s": round(s, 3), "method": "complete build, measured"}
+        parts = 8
+        step = (n + parts - 1) // parts
+        total, labels = 0.0, 0
+        for lo in range(0, n, step):
+            cnt = min(step, n - lo)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            Lp = chl.build(*d, mode="plain", roots=(lo, cnt, 1), stream=stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            total += dt
+            labels += Lp.info()[1]
+            Lp.free()
+            say("plain form: roots [%d, %d) in %.1f s" % (lo, lo + cnt, dt))
+        return {"build_s": round(total, 3), "labels": labels,
+                "method": "complete build, measured: every root grown, in 8 consecutive root ranges timed one "
+                          "after the other"}
     stride = (n - head) // strata
     tp = []
     for roots in ((0, head, 1), (head, strata, stride)):
@@ -308,6 +320,8 @@ def workload(chl, gg, counts, name, dev, stream, reps, plain=None):
     if plain is not None:
         r["plain_form"] = plain_form(chl, d, c["n"], plain[0], plain[1], stream, full=plain[2])
         p = r["plain_form"]
+        if "labels" in p:
+            assert p["labels"] == st["labels"], "%s: the plain form's labels differ in number" % name
         ps = p.get("build_s", p.get("build_s_est"))
         r["plain_form"]["batched_speedup"] = round(ps / b, 1)
     say("workload", name, json.dumps({k: v for k, v in r.items() if k not in ("levels",)}))
@@ -433,6 +447,49 @@ def directed_measure(chl, gg, counts, stream, reps=3):
         r["unpruned_equivalent_gteps"] = round(up["arcs"] / b / 1e9, 2)
     say("directed:", json.dumps(r))
     return r
+
+
+def hybrid_measure(chl, gg, stream, reps=2, psi_th=100):
+    """The Hybrid construction (Section 4.2.1, Psi_th = 100 as the paper sets
+    for scale-free graphs) against PLaNT trees for every root, on R-MAT scale
+    16 under two rankings where the trees explore far more than they label:
+    a random ranking (seed 77), rank-prefix pruning at its default, and the
+    degree ranking with rank-prefix pruning off (the paper's PLaNT). Median
+    of `reps` builds each after one that tunes; the two labelings must be
+    equal (compared on the device)."""
+    import torch
+    dev = torch.device("cuda:0")
+    c = gg.make_config("rmat16")
+    out = []
+    for rank, kw in (("random rank (seed 77)", {}), ("degree rank, rank-prefix pruning off", {"prune_hubs": -1})):
+        order = gg.random_rank(c["n"], 77) if rank.startswith("random") else c["order"]
+        d = dev_inputs(dict(c, order=order), dev)
+        r = {"workload": "R-MAT scale 16 (65,536 vertices, %d edges), %s" % (c["m"], rank), "psi_th": psi_th}
+        labs = []
+        for name, extra in (("plant", {}), ("hybrid", {"hybrid_psi": psi_th})):
+            L = chl.build(*d, stream=stream, **kw, **extra)
+            torch.cuda.synchronize()
+            L.free()
+            b, runs, st, L = timed_builds(chl, d, reps, stream, **kw, **extra)
+            r[name + "_build_s"] = round(b, 4)
+            r[name + "_build_s_runs"] = [round(t, 4) for t in runs]
+            r[name + "_vertex_relaxations"] = int(st["settled"])
+            r[name + "_arcs"] = int(st["arcs"])
+            if name == "hybrid":
+                r.update({"switch_root": int(st["hybrid_switch"]), "psi_at_switch": round(st["hybrid_psi"], 1),
+                          "supersteps": int(st["hybrid_supersteps"]), "pruned_tree_labels": int(st["hybrid_emitted"]),
+                          "cleaned_away": int(st["hybrid_removed"]), "clean_ms": round(st["hybrid_clean_ms"], 2)})
+            r["labels"] = int(st["labels"])
+            labs.append(L.export(dev, stream=stream))
+            torch.cuda.synchronize()
+            L.free()
+        r["same_labels"] = all(bool(torch.equal(x, y)) for x, y in zip(*labs))
+        assert r["same_labels"], "the Hybrid labeling differs from PLaNT's"
+        r["speedup"] = round(r["plant_build_s"] / r["hybrid_build_s"], 2)
+        del labs, d
+        say("hybrid:", json.dumps(r))
+        out.append(r)
+    return out
 
 
 def paths_measure(chl, L, c, d, pairs, stream, reps=3):
@@ -635,6 +692,7 @@ def main():
     for c, L in keep.values():
         L.free()
     directed = directed_measure(chl, gg, counts, stream) if "directed" in sec else None
+    hybrid = hybrid_measure(chl, gg, stream) if "hybrid" in sec else None
     cpu = cpu_baseline(gg, counts, qout_c2, c2 if c2 is not None else gg.make_config("rmat16")) \
         if "cpu" in sec and WORKLOAD == "rmat20" else None
 
@@ -665,6 +723,7 @@ def main():
     out["workloads"] = others or None
     out["serving"] = serving
     out["directed"] = directed
+    out["hybrid"] = hybrid
     out["paths"] = paths
     out["atomics"] = atomics
     print(json.dumps(out))

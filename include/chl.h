@@ -155,6 +155,25 @@ typedef struct chl_build_opts {
                                 afterwards); -1: the batched kernel alone;
                                 0: chosen by the autotuner (off when autotune
                                 is 0). Same labels either way. */
+    int32_t hybrid_psi;      /* batched form, undirected, complete builds: the
+                                Hybrid construction (Section 4.2.1) with
+                                switching threshold Psi_th = hybrid_psi (the
+                                paper uses 100 for scale-free graphs, 500 for
+                                road networks); 0: off (PLaNT trees for every
+                                root). The main phase grows PLaNT trees in
+                                windows of max(64, 8 * roots_in_flight)
+                                consecutive roots; once the vertex relaxations
+                                per label (Psi, Section 4.2.1) of a window's
+                                last max(64, n / 64) trees exceed Psi_th, the
+                                remaining roots grow as
+                                pruned Dijkstra trees with rank queries
+                                (Algorithm 1), in supersteps of
+                                max(64, 2 * roots_in_flight) roots doubling
+                                each time, pruned by the distance query over
+                                every label of the roots before the superstep;
+                                after each superstep its redundant labels are
+                                removed by the cleaning query DQ_Clean
+                                (Algorithm 2). Same labels as without it. */
 } chl_build_opts;
 
 /* Defaults: batched, everything tuned, early termination on, stats on. */
@@ -338,6 +357,18 @@ typedef struct chl_stats {
                                              workgroups per group */
     int64_t small_trees;     /* workgroups of the small-tree kernel in the main
                                 phase (0: not used) */
+    /* Hybrid construction (chl_build_opts::hybrid_psi): the rank position
+       from which the pruned construction grew the roots (n: PLaNT trees
+       throughout; 0 when off), the Psi of the window that triggered it, the
+       supersteps, the labels the pruned trees emitted and those the
+       cleaning removed, and the device time of the cleaning (table
+       regrouping, DQ_Clean, compaction) */
+    int64_t hybrid_switch;
+    double hybrid_psi;
+    int64_t hybrid_supersteps;
+    int64_t hybrid_emitted;
+    int64_t hybrid_removed;
+    double hybrid_clean_ms;
 } chl_stats;
 
 /* Totals into *totals (host, may be NULL). per_root (may be NULL) receives

@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     f"-I{INCLUDE}",
 ]
-SOURCES = ["api.cpp", "prep.hip", "scan.hip", "segsort.hip", "tree.hip", "assemble.hip",
+SOURCES = ["api.cpp", "prep.hip", "scan.hip", "segsort.hip", "tree.hip", "assemble.hip", "hybrid.hip",
            "query.hip", "paths.hip", "microbench.hip", "server.cpp"]
 
 

@@ -51,7 +51,7 @@ class CBuildOpts(C.Structure):
                 ("delta", C.c_int64), ("early_term", C.c_int32), ("stats", C.c_int32),
                 ("autotune", C.c_int32), ("root_count", C.c_int32), ("root_begin", C.c_int32),
                 ("root_stride", C.c_int32), ("prune_hubs", C.c_int32), ("team_wgs", C.c_int32),
-                ("group_levels", C.c_int32), ("small_trees", C.c_int32)]
+                ("group_levels", C.c_int32), ("small_trees", C.c_int32), ("hybrid_psi", C.c_int32)]
 
 
 class CStats(C.Structure):
@@ -61,7 +61,9 @@ class CStats(C.Structure):
             "tree_ms", "prefix_ms", "kernel_ms")] + [("kernel_launches", C.c_int64)] + [
         (f, C.c_double) for f in ("assemble_ms", "prep_ms", "tune_ms")] + [
         ("levels", C.c_int64), ("level_end", C.c_int64 * 16), ("level_ms", C.c_double * 16),
-        ("level_teams", C.c_int64 * 16), ("small_trees", C.c_int64)]
+        ("level_teams", C.c_int64 * 16), ("small_trees", C.c_int64), ("hybrid_switch", C.c_int64),
+        ("hybrid_psi", C.c_double), ("hybrid_supersteps", C.c_int64), ("hybrid_emitted", C.c_int64),
+        ("hybrid_removed", C.c_int64), ("hybrid_clean_ms", C.c_double)]
 
 
 class CServerOpts(C.Structure):
@@ -366,11 +368,12 @@ class Labels:
 
 def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, delta=0,
           early_term=True, stats=True, autotune=True, roots=None, prune_hubs=0, team_wgs=0,
-          stream=None, allocator="torch", directed=False, groups=True, small=None):
+          stream=None, allocator="torch", directed=False, groups=True, small=None, hybrid_psi=0):
     """chl_build over a symmetric CSR (row_ptr int64, col int32, w int32) and a
     ranking order (order[0] most important). roots = (begin, count, stride)
     restricts the build to those root rank positions. directed=True: the CSR
-    holds the out-arcs of a directed graph (chl_build_directed). Returns Labels."""
+    holds the out-arcs of a directed graph (chl_build_directed). hybrid_psi > 0:
+    the Hybrid construction with that switching threshold. Returns Labels."""
     lib = load()
     rp = _dev(row_ptr, torch.int64)
     cl = _dev(col, torch.int32)
@@ -394,6 +397,7 @@ def build(row_ptr, col, w, order, mode="batched", roots_in_flight=0, wg_size=0, 
     o.team_wgs = int(team_wgs)
     o.group_levels = 0 if groups else -1
     o.small_trees = 0 if small is None else (1 if small else -1)
+    o.hybrid_psi = int(hybrid_psi)
     al = allocator if isinstance(allocator, TorchAllocator) else default_allocator() if allocator == "torch" else None
     out = C.c_void_p()
     f = lib.chl_build_directed if directed else lib.chl_build

@@ -193,6 +193,9 @@ struct Build {
     int64_t lv_end[CHL_MAX_LEVELS] = {};
     double lv_ms[CHL_MAX_LEVELS] = {};
     int64_t lv_team[CHL_MAX_LEVELS] = {};
+    // pruned construction of the Hybrid (TreeParams::dhg / rlab)
+    uint32_t* dhg = nullptr;
+    int64_t* rlab = nullptr;
     void record_level(int32_t end, double ms, int team) {
         if (nlev < CHL_MAX_LEVELS) { lv_end[nlev] = end; lv_ms[nlev] = ms; lv_team[nlev] = team; nlev++; }
     }
@@ -275,6 +278,8 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.plab = B.plab;
     p.pbound = B.pbound;
     p.partner = B.partner;
+    p.dhg = B.dhg;
+    p.rlab = B.rlab;
     return p;
 }
 
@@ -894,6 +899,162 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     return 0;
 }
 
+// The Hybrid construction (Section 4.2.1) on one device, for the roots
+// [B.grown, n) that follow the rank-prefix levels. PLaNT trees grow in
+// windows of consecutive roots; the first window whose vertex relaxations
+// per label (Psi) exceed the threshold ends PLaNT. The remaining roots grow
+// in supersteps as pruned Dijkstra trees with rank queries (Algorithm 1,
+// batched kernel phase 3), pruned by the distance query over every label of
+// the roots before the superstep, grouped by vertex; trees of one superstep
+// run concurrently, so each superstep ends with the cleaning query DQ_Clean
+// (Algorithm 2) over its labels, and the kept ones join the groups. The
+// result is the CHL, the same labels as PLaNT trees for every root.
+static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& s, int wg, int64_t delta,
+                      int small_wgs, void* scan_tmp, hipStream_t st, int* launches, chl_stats& S) {
+    const int32_t n = B.n;
+    int32_t lo = B.grown;
+    // per-root statistics feed the Psi monitor
+    int64_t* own_stats = nullptr;
+    if (!B.stats) {
+        own_stats = A.get<int64_t>((size_t)n * STAT_COLS);
+        if (!own_stats) return CHL_ERR_OOM;
+        HIPCHK(hipMemsetAsync(own_stats, 0, (size_t)n * STAT_COLS * 8, st));
+        B.stats = own_stats;
+    }
+    std::vector<int64_t> rows;
+    // windows of 8 trees per slot (at least 64 roots), so that the slots stay
+    // busy; Psi is taken over the window's last n/64 roots (at least 64),
+    // the most recent trees
+    const int64_t win = std::max<int64_t>(64, 8 * (int64_t)s.k);
+    const int64_t recent = std::max<int64_t>(64, n / 64);
+    S.hybrid_switch = n;
+    while (lo < n) {
+        const int32_t hi = (int32_t)std::min<int64_t>(n, (int64_t)lo + win);
+        if (int r = run_batched(A, B, s, wg, delta, o.early_term, nullptr, hi - lo, st, launches, 0, lo, nullptr,
+                                false, nullptr, small_wgs))
+            return r;
+        rows.resize((size_t)(hi - lo) * STAT_COLS);
+        HIPCHK(hipMemcpy(rows.data(), B.stats + (size_t)lo * STAT_COLS, rows.size() * 8, hipMemcpyDeviceToHost));
+        int64_t relaxed = 0, labels = 0;
+        for (int32_t i = (int32_t)std::max<int64_t>(0, (int64_t)(hi - lo) - recent); i < hi - lo; i++) {
+            relaxed += rows[(size_t)i * STAT_COLS];
+            labels += rows[(size_t)i * STAT_COLS + 2];
+        }
+        const double psi = (double)relaxed / (double)std::max<int64_t>(1, labels);
+        lo = hi;
+        if (psi > (double)o.hybrid_psi) {
+            S.hybrid_switch = lo;
+            S.hybrid_psi = psi;
+            break;
+        }
+    }
+    if (lo >= n) {
+        if (own_stats) { A.drop(own_stats); B.stats = nullptr; }
+        return 0;
+    }
+
+    // ---- pruned construction of the roots [lo, n)
+    double clean_ms = 0;
+    int32_t* count = A.get<int32_t>(n);
+    int32_t* fill = A.get<int32_t>(n);
+    int64_t* toff[2] = {A.get<int64_t>((size_t)n + 1), A.get<int64_t>((size_t)n + 1)};
+    uint64_t* tlab[2] = {nullptr, nullptr};
+    size_t tcap[2] = {0, 0};
+    B.dhg = A.get<uint32_t>((size_t)s.k * n);
+    B.rlab = A.get<int64_t>((size_t)2 * n);
+    const int cwg = clean_workgroups(n, n);
+    uint32_t* dc = A.get<uint32_t>((size_t)cwg * n);
+    int64_t* kept_dev = A.get<int64_t>(1);
+    if (A.oom) return CHL_ERR_OOM;
+    HIPCHK(hipMemsetAsync(B.dhg, 0xFF, (size_t)s.k * n * 4, st));
+    HIPCHK(hipMemsetAsync(dc, 0xFF, (size_t)cwg * n * 4, st));
+    // groups of the pool entries [0, to) into buffer b, from the groups of
+    // [0, from) in (off_old, lab_old) (NULL: none, from = 0)
+    auto extend = [&](const int64_t* off_old, const uint64_t* lab_old, unsigned long long from,
+                      unsigned long long to, int b) -> int {
+        if (to > tcap[b]) {
+            if (tlab[b]) A.drop(tlab[b]);
+            tcap[b] = std::max<size_t>(to, 2 * tcap[b]);
+            tlab[b] = A.get<uint64_t>(tcap[b]);
+            if (!tlab[b]) return CHL_ERR_OOM;
+        }
+        if (launch_group_sizes(n, off_old, count, st)) return CHL_ERR_HIP;
+        if (launch_prefix_extend(n, B.pool, off_old ? from : 0, to, count, off_old, lab_old, toff[b], tlab[b], fill,
+                                 scan_tmp, st))
+            return CHL_ERR_HIP;
+        return 0;
+    };
+    // every label so far: the levels' groups (B.poff, the pool entries
+    // [0, B.cursor_base)) and the PLaNT windows' entries after them
+    unsigned long long grouped = B.last_used;
+    const unsigned long long lev = B.poff ? B.cursor_base : 0;
+    if (int r = extend(B.poff, B.plab, lev, grouped, 0)) return r;
+    int cur = 0;
+    int64_t x = std::max<int64_t>(64, 2 * (int64_t)s.k);
+    HostCtl* hc = host_ctl();
+    if (!hc) return CHL_ERR_HIP;
+    while (lo < n) {
+        const int32_t hi = (int32_t)std::min<int64_t>(n, (int64_t)lo + x);
+        B.poff = toff[cur];
+        B.plab = tlab[cur];
+        B.pbound = lo;
+        if (int r = run_batched(A, B, s, wg, delta, o.early_term, nullptr, hi - lo, st, launches, 3, lo)) return r;
+        const unsigned long long used = B.last_used;
+        const unsigned long long cnt = used - grouped;
+        S.hybrid_emitted += (int64_t)cnt;
+        S.hybrid_supersteps++;
+        Timer tc(st);
+        const int nx = 1 - cur;
+        // the superstep's labels join the groups uncleaned: a redundant
+        // label's witness may be a label of the same superstep
+        if (int r = extend(toff[cur], tlab[cur], grouped, used, nx)) return r;
+        int32_t* keep = A.get<int32_t>(std::max<unsigned long long>(1, cnt));
+        int64_t* pos = A.get<int64_t>(cnt + 1);
+        void* stmp = A.get<uint8_t>(scan_temp_bytes((int64_t)std::max<unsigned long long>(1, cnt)));
+        int32_t* tv = A.get<int32_t>(std::max<unsigned long long>(1, cnt));
+        int32_t* th = A.get<int32_t>(std::max<unsigned long long>(1, cnt));
+        int32_t* td = A.get<int32_t>(std::max<unsigned long long>(1, cnt));
+        if (A.oom) return CHL_ERR_OOM;
+        if (launch_clean(lo, hi, n, B.rlab, B.pool, grouped, toff[nx], tlab[nx], dc, keep, B.stats, st))
+            return CHL_ERR_HIP;
+        if (launch_compact(B.pool, grouped, cnt, keep, pos, stmp, tv, th, td, st)) return CHL_ERR_HIP;
+        HIPCHK(hipMemsetAsync(kept_dev, 0, 8, st));
+        if (cnt) HIPCHK(hipMemcpyAsync(kept_dev, pos + cnt, 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(hc->c64, kept_dev, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const unsigned long long kept = hc->c64[0];
+        if (kept) {
+            HIPCHK(hipMemcpyAsync(B.pool.v + grouped, tv, kept * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(B.pool.hub + grouped, th, kept * 4, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(B.pool.dist + grouped, td, kept * 4, hipMemcpyDeviceToDevice, st));
+        }
+        const unsigned long long end = grouped + kept;
+        HIPCHK(hipMemcpyAsync(B.ctl64, &end, 8, hipMemcpyHostToDevice, st));
+        // the groups again, from the kept labels only
+        if (int r = extend(toff[cur], tlab[cur], grouped, end, nx)) return r;
+        clean_ms += tc.stop();
+        A.drop(keep);
+        A.drop(pos);
+        A.drop(stmp);
+        A.drop(tv);
+        A.drop(th);
+        A.drop(td);
+        S.hybrid_removed += (int64_t)(cnt - kept);
+        grouped = end;
+        B.last_used = end;
+        cur = nx;
+        lo = hi;
+        x *= 2;
+    }
+    S.hybrid_clean_ms = clean_ms;
+    B.dhg = nullptr;
+    B.rlab = nullptr;
+    B.poff = toff[cur];
+    B.plab = tlab[cur];
+    if (own_stats) { A.drop(own_stats); B.stats = nullptr; }
+    return 0;
+}
+
 static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_build_opts* opts_in,
                           const chl_allocator* alloc_in, void* stream, chl_labels** out, bool directed) {
     if (!g || !order || !out) return CHL_ERR_INVALID_ARG;
@@ -914,6 +1075,9 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (o.team_wgs < 0 || o.team_wgs > 16) return CHL_ERR_INVALID_ARG;
     if (o.group_levels < -1 || o.group_levels > 0) return CHL_ERR_INVALID_ARG;
     if (o.small_trees < -1 || o.small_trees > 1) return CHL_ERR_INVALID_ARG;
+    // the Hybrid construction: batched form, complete undirected builds
+    if (o.hybrid_psi < 0) return CHL_ERR_INVALID_ARG;
+    if (o.hybrid_psi > 0 && (o.mode != CHL_MODE_BATCHED || o.root_count > 0 || directed)) return CHL_ERR_INVALID_ARG;
     if (o.root_count > 0) {
         if (o.root_stride < 1 || o.root_begin < 0 || o.root_begin >= g->n) return CHL_ERR_INVALID_ARG;
         if ((int64_t)o.root_begin + (int64_t)(o.root_count - 1) * o.root_stride >= g->n) return CHL_ERR_INVALID_ARG;
@@ -1055,6 +1219,8 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
         for (int32_t i = 0; i < o.root_count; i++) sel.push_back(o.root_begin + i * o.root_stride);
     int r = o.mode == CHL_MODE_PLAIN
                 ? run_plain(A, B, s, wg, delta, o.early_term, sel, st, &launches)
+            : o.hybrid_psi > 0
+                ? run_hybrid(A, B, o, s, wg, delta, (int)S.small_trees, scan_tmp, st, &launches, S)
                 : run_batched(A, B, s, wg, delta, o.early_term, sel.empty() ? nullptr : sel.data(),
                               sel.empty() ? n - grown : (int32_t)sel.size(), st, &launches, 0,
                               sel.empty() ? grown : 0, nullptr, false, nullptr, (int)S.small_trees);

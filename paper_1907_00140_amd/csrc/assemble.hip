@@ -156,6 +156,11 @@ int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partn
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_old_sizes, dim3(g(n)), dim3(256), 0, st, n, off, count);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
                          const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
                          int32_t* fill, void* scan_temp, hipStream_t st) {

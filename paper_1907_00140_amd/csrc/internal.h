@@ -92,6 +92,12 @@ struct TreeParams {
     // distances to the prefix hubs are those of its partner h ^ 1 from the
     // hubs x ^ 1, d(h, x) being d'(x ^ 1, h ^ 1) on the reversed copy; 0 else
     int32_t partner;
+    // pruned construction of the Hybrid (batched form, phase 3): the root's
+    // distances to the hubs [0, pbound) in dhg, n words per slot, all ones
+    // between trees (pbound may exceed what LDS holds); every tree's pool
+    // range in rlab[2 * root] = first entry, rlab[2 * root + 1] = count
+    uint32_t* dhg;
+    int64_t* rlab;
     // outputs
     int64_t* stats;         // [n][STAT_COLS] by root or NULL
     int32_t* err;
@@ -188,6 +194,24 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
 int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
                          const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
                          int32_t* fill, void* scan_temp, hipStream_t st);
+// assemble.hip: count[v] = size of v's group in off (0 for every v when
+// off is NULL): the running sizes that launch_prefix_extend continues from
+int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st);
+// hybrid.hip: the cleaning query DQ_Clean (Algorithm 2) over the labels of
+// the roots [lo, hi), whose pool ranges rlab holds (first entry, count per
+// root) inside [from, ...); (poff, plab) groups every label so far by vertex,
+// those of [lo, hi) included. keep[i - from] = 0 for a redundant label, 1
+// else; stats (may be NULL) gets each root's kept label count in column 2.
+// dcbuf: clean_workgroups(hi - lo, n) * n words, all ones (left so).
+int clean_workgroups(int32_t nroots, int32_t n);
+int launch_clean(int32_t lo, int32_t hi, int32_t n, const int64_t* rlab, const Pool& pool, uint64_t from,
+                 const int64_t* poff, const uint64_t* plab, uint32_t* dcbuf, int32_t* keep, int64_t* stats,
+                 hipStream_t st);
+// hybrid.hip: the pool entries [from, from + cnt) whose keep flag is 1, in
+// order, into (tv, th, td); pos receives cnt + 1 exclusive sums (pos[cnt] =
+// entries kept); scan_temp holds scan_temp_bytes(cnt)
+int launch_compact(const Pool& pool, uint64_t from, uint64_t cnt, const int32_t* keep, int64_t* pos, void* scan_temp,
+                   int32_t* tv, int32_t* th, int32_t* td, hipStream_t st);
 // assemble.hip: the roots [g, g2) of a pruning level into roots[0, g2 - g),
 // most prefix labels first (poff: the prefix groups; a directed build counts
 // the group of the partner h ^ 1 when it lies in [g, g2)), ties by rank; keys

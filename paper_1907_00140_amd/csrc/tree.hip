@@ -165,7 +165,8 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                                             int32_t* far, C* cnt_touched, C* cnt_next,
                                             C* cnt_far, C* cnt_far_clean, unsigned long long* umax,
                                             const int64_t* poff, const uint64_t* plab, uint32_t pbound,
-                                            const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs) {
+                                            const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs,
+                                            bool rank_query = false) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -220,6 +221,9 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
             // current one: when the candidate is not below it, the atomic
             // would fail and is skipped.
             bool cand = valid && nk < seen[j];
+            // rank query of the pruned construction (Algorithm 1): a vertex
+            // that outranks the root is neither labelled nor expanded
+            if (rank_query && u < h) cand = false;
             if (cand && dh) {
                 // Rank-prefix pruning (Section 4.3): the labels of the hubs
                 // [0, pbound), complete because their trees are done, give the
@@ -329,17 +333,24 @@ __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, con
     return cl == 0 && lb > S.umax;
 }
 
-// PHASE only names the launch (0: main phase of a build, 1: autotuner probe,
+// PHASE names the launch (0: main phase of a build, 1: autotuner probe,
 // 2: the common-label roots grown before the main phase), so that profiles
-// separate them. PRUNE: rank-prefix pruning with p.poff / p.plab; the root's
-// distances to the prefix hubs live in dynamic LDS (p.pbound words).
+// separate them; PHASE 3 is the pruned construction of the Hybrid
+// (Section 4.2.1): pruned Dijkstra with rank queries (Algorithm 1), every
+// vertex it reaches labelled, the distance queries answered by all labels
+// of the hubs [0, p.pbound), the root's side in the global p.dhg, and each
+// tree's pool range recorded in p.rlab for the cleaning that follows.
+// PRUNE: rank-prefix pruning with p.poff / p.plab; the root's distances to
+// the prefix hubs live in dynamic LDS (p.pbound words) below phase 3.
 template <typename K, int WG, int PHASE, bool PRUNE>
 __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
+    constexpr bool HYB = PHASE == 3;
     __shared__ BatchedLds<K, WG> S;
-    extern __shared__ uint32_t dh[];
+    extern __shared__ uint32_t dh_lds[];
     const int tid = threadIdx.x;
     const int64_t slot = blockIdx.x;
+    uint32_t* dh = HYB ? p.dhg + slot * p.s.stride : dh_lds;
     K* key = (K*)p.s.key + slot * p.s.stride;
     uint32_t* flags = p.s.flags + slot * p.s.fstride;
     int32_t* touched = p.s.touched + slot * p.s.stride;
@@ -347,8 +358,9 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     int32_t* far = lists + 2 * p.s.stride;
     const int64_t delta = p.delta;
     // dh is all ones between trees: a tree sets its root's entries and
-    // clears them when it is done
-    if (PRUNE)
+    // clears them when it is done (the global array of phase 3 is set to
+    // all ones when it is allocated)
+    if (PRUNE && !HYB)
         for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
     if (tid == 0) { S.bnext = 0; S.bend = 0; }
 
@@ -425,7 +437,7 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                     relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
                                            &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, p.poff,
-                                           p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs);
+                                           p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, HYB);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
@@ -535,6 +547,10 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             }
         }
         if (ovf) atomicOr(p.err, ERR_BIT_OVERFLOW);
+        if (HYB && tid == 0 && pb >= 0) {
+            p.rlab[2 * (int64_t)h] = pb;
+            p.rlab[2 * (int64_t)h + 1] = nl;
+        }
         if (p.stats && tid == 0) {
             // every thread of the block accumulated the same settled / arc counts
             int64_t* s = p.stats + (int64_t)h * STAT_COLS;
@@ -1963,7 +1979,10 @@ int launch_batched_t(const TreeParams& p, int phase, hipStream_t st) {
     const bool pr = p.poff != nullptr && p.pbound > 0;
     const size_t dl = pr ? (size_t)p.pbound * 4 : 0;
     const dim3 g(p.s.k), b(WG);
-    if (phase == 1 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true>), g, b, dl, st, p);
+    if (phase == 3) {
+        if (!pr || !p.dhg || !p.rlab) return -1;
+        hipLaunchKernelGGL((k_tree_batched<K, WG, 3, true>), g, b, 0, st, p);
+    } else if (phase == 1 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true>), g, b, dl, st, p);
     else if (phase == 1) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, false>), g, b, 0, st, p);
     else if (phase == 2 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, true>), g, b, dl, st, p);
     else if (phase == 2) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, false>), g, b, 0, st, p);
