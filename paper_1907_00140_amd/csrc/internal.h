@@ -98,6 +98,9 @@ struct TreeParams {
     // range in rlab[2 * root] = first entry, rlab[2 * root + 1] = count
     uint32_t* dhg;
     int64_t* rlab;
+    // team and group launches: 1 = a team's workgroups are taken from one
+    // XCD (workgroup b of a launch runs on XCD b % 8), 0 = consecutive ids
+    int32_t xcd_map;
     // outputs
     int64_t* stats;         // [n][STAT_COLS] by root or NULL
     int32_t* err;

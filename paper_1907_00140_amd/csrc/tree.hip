@@ -812,6 +812,15 @@ __device__ __forceinline__ bool team_sync(long long* tw, int W, unsigned long lo
     return S.ok != 0;
 }
 
+// The dispatcher hands the workgroups of a launch to the eight XCDs in turn
+// (workgroup b to XCD b % 8), each XCD with its own L2. With xcd_map set, a
+// launch of G workgroups (G a multiple of 8) numbers them XCD by XCD, so
+// that a team of consecutive numbers shares one L2 (W dividing G / 8) or
+// two.
+__device__ __forceinline__ int team_index(int b, int G, int xcd_map) {
+    return xcd_map && G % 8 == 0 ? (b % 8) * (G / 8) + b / 8 : b;
+}
+
 template <typename K, int WG, bool PRUNE>
 __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long* tstate, int32_t* far2_all) {
     constexpr int SC = __HIP_MEMORY_SCOPE_AGENT;
@@ -819,7 +828,8 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
     __shared__ TeamLds<K, WG> S;
     extern __shared__ uint32_t dh[];
     const int tid = threadIdx.x;
-    const int team = blockIdx.x / W, trank = blockIdx.x % W;
+    const int lb = team_index(blockIdx.x, gridDim.x, p.xcd_map);
+    const int team = lb / W, trank = lb % W;
     const int64_t tgtid = (int64_t)trank * WG + tid, tthreads = (int64_t)W * WG;
     const bool leader = trank == 0 && tid == 0;
     long long* tw = tstate + (int64_t)team * TEAM_WORDS;
@@ -1624,7 +1634,8 @@ __global__ __launch_bounds__(WG) void k_tree_group(TreeParams p, int W, long lon
     __shared__ GroupLds<K, WG> S;
     extern __shared__ uint32_t dh[];     // [GT][pbound]: each tree's root distances to the prefix hubs
     const int tid = threadIdx.x;
-    const int team = blockIdx.x / W, trank = blockIdx.x % W;
+    const int lb = team_index(blockIdx.x, gridDim.x, p.xcd_map);
+    const int team = lb / W, trank = lb % W;
     const int64_t tgtid = (int64_t)trank * WG + tid, tthreads = (int64_t)W * WG;
     const bool leader = trank == 0 && tid == 0;
     const int32_t n = p.g.n;
