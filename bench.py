@@ -139,12 +139,19 @@ def level_table(counts, name, st):
     lo = 0
     for i, (end, ms, tw) in enumerate(zip(st["level_end"], st["level_ms"], st["level_teams"])):
         r = {"roots": [lo, int(end)], "team_wgs": int(tw), "ms": round(ms, 3)}
+        if "per_root" in st:
+            r["gpu_arcs"] = int(st["per_root"][lo:int(end), 1].sum())
         if e is not None and i < len(e["levels"]):
             u = e["levels"][i][2]
             r["oracle_arcs"] = u["arcs"]
             r["alg_gbs"] = round(alg_bytes(u) / (ms / 1e3) / 1e9, 1) if ms > 0 else None
         rows.append(r)
         lo = int(end)
+    if "per_root" in st and st["level_end"]:
+        r = {"roots": [lo, int(st["n"])], "main_phase": True, "gpu_arcs": int(st["per_root"][lo:, 1].sum())}
+        if e is not None:
+            r["oracle_arcs"] = e["rest"]["arcs"]
+        rows.append(r)
     return rows
 
 
@@ -322,6 +329,15 @@ def workload(chl, gg, counts, name, dev, stream, reps, plain=None):
         p = r["plain_form"]
         if "labels" in p:
             assert p["labels"] == st["labels"], "%s: the plain form's labels differ in number" % name
+        if name.startswith("rmat"):
+            # like for like: the plain form grows unpruned trees, so it is set
+            # beside the batched form without rank-prefix pruning as well
+            Lu = chl.build(*d, stream=stream, prune_hubs=-1)
+            Lu.free()
+            bu, _, _, Lu = timed_builds(chl, d, 2, stream, prune_hubs=-1)
+            Lu.free()
+            p["batched_unpruned_s"] = round(bu, 4)
+            p["unpruned_batched_speedup"] = round(p.get("build_s", p.get("build_s_est")) / bu, 1)
         ps = p.get("build_s", p.get("build_s_est"))
         r["plain_form"]["batched_speedup"] = round(ps / b, 1)
     say("workload", name, json.dumps({k: v for k, v in r.items() if k not in ("levels",)}))
