@@ -161,11 +161,12 @@ typedef struct chl_build_opts {
                                 paper uses 100 for scale-free graphs, 500 for
                                 road networks); 0: off (PLaNT trees for every
                                 root). The main phase grows PLaNT trees in
-                                windows of max(64, 8 * roots_in_flight)
-                                consecutive roots; once the vertex relaxations
-                                per label (Psi, Section 4.2.1) of a window's
-                                last max(64, n / 64) trees exceed Psi_th, the
-                                remaining roots grow as
+                                windows of consecutive roots, the first of
+                                r = max(64, n / 64) roots, each next one twice
+                                as large up to max(r, 8 * roots_in_flight);
+                                once the vertex relaxations per label (Psi,
+                                Section 4.2.1) of a window's last r trees
+                                exceed Psi_th, the remaining roots grow as
                                 pruned Dijkstra trees with rank queries
                                 (Algorithm 1), in supersteps of
                                 max(64, 2 * roots_in_flight) roots doubling

@@ -925,11 +925,13 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
         B.stats = own_stats;
     }
     std::vector<int64_t> rows;
-    // windows of 8 trees per slot (at least 64 roots), so that the slots stay
-    // busy; Psi is taken over the window's last n/64 roots (at least 64),
-    // the most recent trees
-    const int64_t win = std::max<int64_t>(64, 8 * (int64_t)s.k);
+    // Psi is taken over the last n/64 roots (at least 64) of a window, the
+    // most recent trees; the first window holds that many roots and each
+    // next one twice as many, up to 8 trees per slot, so that the switch
+    // point is resolved finely early on and the slots stay busy later
     const int64_t recent = std::max<int64_t>(64, n / 64);
+    const int64_t wmax = std::max<int64_t>(recent, 8 * (int64_t)s.k);
+    int64_t win = recent;
     S.hybrid_switch = n;
     while (lo < n) {
         const int32_t hi = (int32_t)std::min<int64_t>(n, (int64_t)lo + win);
@@ -950,6 +952,7 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
             S.hybrid_psi = psi;
             break;
         }
+        win = std::min<int64_t>(wmax, 2 * win);
     }
     if (lo >= n) {
         if (own_stats) { A.drop(own_stats); B.stats = nullptr; }
