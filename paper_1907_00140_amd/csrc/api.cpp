@@ -724,12 +724,14 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     // level 0
     int32_t g = std::min<int32_t>(16, gmax);
     // the first levels hold the largest trees: 1024-thread workgroups,
-    // teams of them for the narrow levels. Buckets of half the mean
-    // weight for the unpruned trees of level 0 (wider ones cost
-    // re-relaxation, narrower ones team barriers), twice the mean weight
-    // for the pruned levels, whose trees are smaller and latency bound
-    // (measured on R-MAT scales 16 and 20)
-    const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 2));
+    // teams of them for the narrow levels. Buckets of a quarter of the
+    // mean weight for the unpruned trees of level 0 (wider ones cost
+    // re-relaxation: R-MAT 20's level 0 relaxes 3.85x the oracle's arcs
+    // at half the mean weight, 3.6x at a quarter; narrower ones cost more
+    // team barriers than they save: an eighth relaxes 2.6x and takes as
+    // long), twice the mean weight for the pruned levels, whose trees are
+    // smaller and latency bound (measured on R-MAT scales 16 and 20)
+    const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 4));
     const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
     // levels with fewer trees than the device holds workgroups of that
     // size run as teams of workgroups, one tree per team
