@@ -728,8 +728,9 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     // mean weight for the unpruned trees of level 0 (wider ones cost
     // re-relaxation: R-MAT 20's level 0 relaxes 3.85x the oracle's arcs
     // at half the mean weight, 3.6x at a quarter; narrower ones cost more
-    // team barriers than they save: an eighth relaxes 2.6x and takes as
-    // long), twice the mean weight for the pruned levels, whose trees are
+    // team barriers than they save: an eighth relaxes 3.2x and takes as
+    // long, a sixteenth 2.6x and takes longer), twice the mean weight for
+    // the pruned levels, whose trees are
     // smaller and latency bound (measured on R-MAT scales 16 and 20)
     const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 4));
     const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
