@@ -730,8 +730,8 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     // at half the mean weight, 3.6x at a quarter; narrower ones cost more
     // team barriers than they save: an eighth relaxes 3.2x and takes as
     // long, a sixteenth 2.6x and takes longer), twice the mean weight for
-    // the pruned levels, whose trees are
-    // smaller and latency bound (measured on R-MAT scales 16 and 20)
+    // the pruned levels, whose trees are smaller and latency bound
+    // (measured on R-MAT scales 16 and 20)
     const int64_t dl = std::max<int64_t>(1, (int64_t)(wm / 4));
     const int64_t dl1 = std::max<int64_t>(1, (int64_t)(2 * wm));
     // levels with fewer trees than the device holds workgroups of that
