@@ -180,6 +180,7 @@ struct Build {
     // rank-prefix pruning: labels found so far, grouped by rank position
     const int64_t* poff = nullptr;
     const uint64_t* plab = nullptr;
+    uint32_t* pmin = nullptr;            // lower bound of each vertex's group distances
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
     int32_t partner = 0;                 // combined graph of a directed build (TreeParams::partner)
     unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
@@ -276,6 +277,7 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.pop_batch = std::max(1, std::min(16, nroots / std::max(1, 8 * s.k)));
     p.poff = B.poff;
     p.plab = B.plab;
+    p.pmin = B.pmin;
     p.pbound = B.pbound;
     p.partner = B.partner;
     p.dhg = B.dhg;
@@ -688,7 +690,9 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     int32_t* pcount = A.get<int32_t>(n);
     int32_t* pfill = A.get<int32_t>(n);
     int64_t* poff[2] = {A.get<int64_t>((size_t)n + 1), A.get<int64_t>((size_t)n + 1)};
+    B.pmin = A.get<uint32_t>(n);
     if (A.oom) return CHL_ERR_OOM;
+    HIPCHK(hipMemsetAsync(B.pmin, 0xFF, (size_t)n * 4, st));
     uint64_t* plab[2] = {nullptr, nullptr};
     size_t plab_cap[2] = {0, 0};
     int cur = -1;                       // buffer holding the groups so far
@@ -712,7 +716,8 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
             if (!plab[nx]) return CHL_ERR_OOM;
         }
         if (launch_prefix_extend(n, B.pool, grouped, used, pcount, cur < 0 ? nullptr : poff[cur],
-                                 cur < 0 ? nullptr : plab[cur], poff[nx], plab[nx], pfill, scan_tmp, st))
+                                 cur < 0 ? nullptr : plab[cur], poff[nx], plab[nx], pfill, scan_tmp, st) ||
+            launch_group_min(B.pool, grouped, used, B.pmin, st))
             return CHL_ERR_HIP;
         cur = nx;
         grouped = used;
@@ -998,6 +1003,14 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
     unsigned long long grouped = B.last_used;
     const unsigned long long lev = B.poff ? B.cursor_base : 0;
     if (int r = extend(B.poff, B.plab, lev, grouped, 0)) return r;
+    if (!B.pmin) {
+        B.pmin = A.get<uint32_t>(n);
+        if (!B.pmin) return CHL_ERR_OOM;
+        HIPCHK(hipMemsetAsync(B.pmin, 0xFF, (size_t)n * 4, st));
+        if (launch_group_min(B.pool, 0, grouped, B.pmin, st)) return CHL_ERR_HIP;
+    } else if (launch_group_min(B.pool, lev, grouped, B.pmin, st)) {
+        return CHL_ERR_HIP;
+    }
     int cur = 0;
     int64_t x = std::max<int64_t>(64, 2 * (int64_t)s.k);
     HostCtl* hc = host_ctl();
@@ -1041,6 +1054,7 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
         HIPCHK(hipMemcpyAsync(B.ctl64, &end, 8, hipMemcpyHostToDevice, st));
         // the groups again, from the kept labels only
         if (int r = extend(toff[cur], tlab[cur], grouped, end, nx)) return r;
+        if (launch_group_min(B.pool, grouped, end, B.pmin, st)) return CHL_ERR_HIP;
         clean_ms += tc.stop();
         A.drop(keep);
         A.drop(pos);

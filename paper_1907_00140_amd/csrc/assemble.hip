@@ -156,6 +156,20 @@ int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partn
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+__global__ void k_group_min(const int32_t* __restrict__ pv, const int32_t* __restrict__ pd, uint64_t cnt,
+                            uint32_t* __restrict__ pmin) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        atomicMin(&pmin[pv[i]], (uint32_t)pd[i]);
+}
+
+int launch_group_min(const Pool& pool, uint64_t from, uint64_t to, uint32_t* pmin, hipStream_t st) {
+    if (to <= from) return 0;
+    hipLaunchKernelGGL(k_group_min, dim3(g(to - from)), dim3(256), 0, st, pool.v + from, pool.dist + from, to - from,
+                       pmin);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st) {
     hipLaunchKernelGGL(k_old_sizes, dim3(g(n)), dim3(256), 0, st, n, off, count);
     return hipGetLastError() == hipSuccess ? 0 : -1;

@@ -87,6 +87,10 @@ struct TreeParams {
     const int64_t* poff;
     const uint64_t* plab;
     int32_t pbound;
+    // pmin[v] <= every distance in v's group (NULL: none): a walk through a
+    // prefix hub from root h to v is at least (h's smallest prefix distance)
+    // + pmin[v], so a candidate below that bound skips reading v's group
+    const uint32_t* pmin;
     // 1 for the combined graph of a directed build (the graph's vertices at
     // even rank positions 2i, their reversed copies at 2i + 1): a root's
     // distances to the prefix hubs are those of its partner h ^ 1 from the
@@ -197,6 +201,10 @@ int launch_assemble(int32_t n, const int32_t* order, const Pool& pool, uint64_t 
 int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t used, int32_t* count,
                          const int64_t* off_old, const uint64_t* lab_old, int64_t* off_new, uint64_t* lab_new,
                          int32_t* fill, void* scan_temp, hipStream_t st);
+// assemble.hip: pmin[v] = min(pmin[v], distance) over the pool entries
+// [from, to) of v (pmin starts all ones and only decreases, so it stays a
+// lower bound of v's group when entries leave it)
+int launch_group_min(const Pool& pool, uint64_t from, uint64_t to, uint32_t* pmin, hipStream_t st);
 // assemble.hip: count[v] = size of v's group in off (0 for every v when
 // off is NULL): the running sizes that launch_prefix_extend continues from
 int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st);

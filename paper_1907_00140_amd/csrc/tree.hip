@@ -166,7 +166,8 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                                             C* cnt_far, C* cnt_far_clean, unsigned long long* umax,
                                             const int64_t* poff, const uint64_t* plab, uint32_t pbound,
                                             const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs,
-                                            bool rank_query = false) {
+                                            bool rank_query = false, const uint32_t* pmin = nullptr,
+                                            uint32_t dhmin = 0) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -224,7 +225,9 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
             // rank query of the pruned construction (Algorithm 1): a vertex
             // that outranks the root is neither labelled nor expanded
             if (rank_query && u < h) cand = false;
-            if (cand && dh) {
+            // no walk through a prefix hub is shorter than the root's nearest
+            // prefix hub plus u's: below that bound u's group is not read
+            if (cand && dh && (!pmin || (uint64_t)dhmin + pmin[u] <= nd)) {
                 // Rank-prefix pruning (Section 4.3): the labels of the hubs
                 // [0, pbound), complete because their trees are done, give the
                 // length of the shortest root-u walk through each of them
@@ -286,6 +289,7 @@ struct BatchedLds {
     int32_t ncur, cnt_next, cnt_far, cnt_touched, nkeep, far_clean;
     int32_t root;
     int32_t bnext, bend;      // root queue positions taken by this workgroup, not yet grown
+    uint32_t dhmin;           // smallest distance of the root to a prefix hub
     unsigned long long umax;
     long long pool_base;
 };
@@ -385,6 +389,7 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                 S.bnext++;
             }
             S.root = r;
+            S.dhmin = 0xFFFFFFFFu;
         }
         __syncthreads();
         const int32_t h = S.root;
@@ -396,7 +401,10 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
                 const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
-                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = (uint32_t)lx;
+                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
+                    dh[y] = (uint32_t)lx;
+                    atomicMin(&S.dhmin, (uint32_t)lx);
+                }
             }
 
         // ---- init: root key (0, clean) in near list 0
@@ -437,7 +445,8 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                     relax_block<K, WG, SC>(p.g, key, flags, cur, base, min(WG, ncur - base), curbit,
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
                                            &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, p.poff,
-                                           p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, HYB);
+                                           p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, HYB,
+                                           p.pmin, S.dhmin);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
@@ -766,6 +775,7 @@ struct TeamLds {
     Expand<K, WG> X;
     unsigned long long red64[WG / 64];
     int ok;
+    uint32_t dhmin;           // smallest distance of the root to a prefix hub
 };
 
 template <typename T>
@@ -875,13 +885,17 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
         const bool prune = PRUNE && h >= p.pbound;
         if (prune) {
             for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
+            if (tid == 0) S.dhmin = 0xFFFFFFFFu;
             __syncthreads();
             const uint32_t px = (uint32_t)p.partner;
             const int32_t hg = h ^ (int32_t)px;      // whose prefix labels give d(h, x)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
                 const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
-                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = (uint32_t)lx;
+                if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
+                    dh[y] = (uint32_t)lx;
+                    atomicMin(&S.dhmin, (uint32_t)lx);
+                }
             }
             __syncthreads();
         }
@@ -938,7 +952,8 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
                                            nextbit, h, T, touched, next, far, (ull*)&tw[T_TOUCHED],
                                            (ull*)&tw[T_CNT0 + (it + 1) % 3], (ull*)&tw[T_FAR],
                                            (ull*)&tw[T_FARCLEAN], (ull*)&tw[T_UMAX], p.poff, p.plab,
-                                           (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs);
+                                           (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, false,
+                                           p.pmin, S.dhmin);
                 if (leader) {
                     tws(tw, T_CNT0 + (it + 2) % 3, 0);
                     tws(tw, T_SETTLED, twl<long long>(tw, T_SETTLED) + ncur);
@@ -1080,6 +1095,7 @@ struct SmallLds {
     int32_t red32[1];
     int32_t ncur, cnt_next, cnt_far, nkeep, far_clean, nused, bad, fill;
     int32_t root, bnext, bend;
+    uint32_t dhmin;                  // smallest distance of the root to a prefix hub
     unsigned long long umax;
     long long pool_base;
 };
@@ -1180,9 +1196,10 @@ __device__ __forceinline__ void srelax(const TreeParams& p, SmallLds<K>& S, cons
             int su = valid ? slookup(S, u) : -1;
             const K seen = su >= 0 ? __hip_atomic_load(&S.keys[su], __ATOMIC_RELAXED, SCW) : KeyTraits<K>::INF;
             bool cand = valid && nk < seen;
-            if (PRUNE && cand) {
+            if (PRUNE && cand && (!p.pmin || (uint64_t)S.dhmin + p.pmin[u] <= nd)) {
                 // rank-prefix pruning (Section 4.3), as in the other forms,
-                // with the root's prefix distances from the LDS table
+                // with the root's prefix distances from the LDS table (and
+                // the same bound)
                 const int64_t lb = p.poff[u], le = p.poff[u + 1];
                 for (int64_t i = lb; i < le && cand; i += 4) {
                     uint64_t lx[4];
@@ -1264,6 +1281,7 @@ __global__ __launch_bounds__(64) void k_tree_small(TreeParams p, int32_t* ovf, i
             S.root = r;
             S.ncur = 1; S.cnt_next = 0; S.cnt_far = 0; S.far_clean = 0; S.umax = 0; S.bad = 0; S.nused = 0;
             S.fill = 0;
+            S.dhmin = 0xFFFFFFFFu;
         }
         __syncthreads();
         const int32_t h = S.root;
@@ -1283,6 +1301,7 @@ __global__ __launch_bounds__(64) void k_tree_small(TreeParams p, int32_t* ovf, i
                     if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
                         uint32_t s = shash(y, SPH);
                         while (atomicCAS(&S.phub[s], S_EMPTY, (int32_t)y) != S_EMPTY) s = (s + 1) & (SPH - 1);
+                        atomicMin(&S.dhmin, (uint32_t)lx);
                         S.pdist[s] = (uint32_t)lx;
                     }
                 }
@@ -1509,6 +1528,7 @@ struct GroupLds {
     unsigned long long lmin[GT], lumax[GT];
     uint32_t lcl[GT], lfcl[GT];
     unsigned long long lset[GT], larc[GT], lnl[GT];
+    uint32_t dhmin[GT];       // each tree's smallest distance to a prefix hub
     int ok;
 };
 
@@ -1570,9 +1590,9 @@ __device__ __forceinline__ void group_relax(const TreeParams& p, const GroupCtx<
             const uint64_t nd = (uint64_t)(kv[j] >> 1) + (uint32_t)a[j];
             const K nk = pack<K>(nd, (uint32_t)(kv[j] & 1) & (uint32_t)(u > h));
             bool cand = valid && nk < seen[j];
-            if (PRUNE && cand && cx.pb) {
+            if (PRUNE && cand && cx.pb && (!p.pmin || (uint64_t)S.dhmin[b] + p.pmin[u] <= nd)) {
                 // rank-prefix pruning (Section 4.3), as in the other forms,
-                // with this tree's root distances
+                // with this tree's root distances (and the same bound)
                 const uint32_t* dhb = dh + (int64_t)b * cx.pb;
                 const int64_t lb = p.poff[u], le = p.poff[u + 1];
                 for (int64_t i = lb; i < le && cand; i += 4) {
@@ -1695,6 +1715,7 @@ __global__ __launch_bounds__(WG) void k_tree_group(TreeParams p, int W, long lon
             // each tree's distances to the prefix hubs, from its root's
             // prefix labels (a directed build reads the partner's)
             for (int64_t x = tid; x < (int64_t)GT * pb; x += WG) dh[x] = 0xFFFFFFFFu;
+            if (tid < GT) S.dhmin[tid] = 0xFFFFFFFFu;
             __syncthreads();
             const uint32_t px = (uint32_t)p.partner;
             for (int b = 0; b < GT; b++) {
@@ -1704,7 +1725,10 @@ __global__ __launch_bounds__(WG) void k_tree_group(TreeParams p, int W, long lon
                 for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                     const uint64_t lx = p.plab[i];
                     const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
-                    if (x < pb && y < pb) dh[b * pb + y] = (uint32_t)lx;
+                    if (x < pb && y < pb) {
+                        dh[b * pb + y] = (uint32_t)lx;
+                        atomicMin(&S.dhmin[b], (uint32_t)lx);
+                    }
                 }
             }
             __syncthreads();
