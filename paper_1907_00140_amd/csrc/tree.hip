@@ -457,6 +457,9 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             // ---- bucket done: drop settled far entries, find the smallest
             //      pending distance and whether any pending vertex is clean
             int32_t nfar = S.cnt_far;
+            // nothing pending at all (most trees of the main phase end so):
+            // the tree is complete without the filter's reductions
+            if (nfar == 0) break;
             if (tid == 0) { S.nkeep = 0; }
             __syncthreads();
             unsigned long long mymin = ~0ull;
