@@ -79,3 +79,36 @@ def test_build_entry_resolves_the_build_module():
     assert callable(b.build)
     import __graft_entry__ as ge
     assert callable(ge.build) and callable(ge.smoke)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's field
+    offsets and sizes (a field added on one side only would shift every
+    later one)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    from paper_1907_00140_amd import chl
+    mirrors = {"chl_graph": chl.CGraph, "chl_allocator": chl.CAllocator, "chl_build_opts": chl.CBuildOpts,
+               "chl_stats": chl.CStats, "chl_server_opts": chl.CServerOpts}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "chl.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, cls in mirrors.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
