@@ -181,6 +181,7 @@ struct Build {
     const int64_t* poff = nullptr;
     const uint64_t* plab = nullptr;
     uint32_t* pmin = nullptr;            // lower bound of each vertex's group distances
+    int32_t dmaj = 0;                    // plab entries (dist << 32) | hub, groups by distance (TreeParams::dmaj)
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
     int32_t partner = 0;                 // combined graph of a directed build (TreeParams::partner)
     unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
@@ -278,6 +279,7 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.poff = B.poff;
     p.plab = B.plab;
     p.pmin = B.pmin;
+    p.dmaj = B.dmaj;
     p.pbound = B.pbound;
     p.partner = B.partner;
     p.dhg = B.dhg;
@@ -1218,6 +1220,23 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     double tune_ms = 0;
     bool small = false;
     if (int r = pick_params(A, B, g, o, st, k, wg, delta, small, tune_ms)) return r;
+    // The main phase reads the prefix groups ordered by distance: a
+    // candidate's pruning test then stops at the first entry whose distance,
+    // plus the root's nearest prefix hub, exceeds the candidate (no later
+    // entry can give a shorter walk). R-MAT 20: main phase 41.4 -> 32.7 ms
+    // for a 1.8 ms sort of 48 M entries. (The small-tree kernel and the
+    // Hybrid read the groups in hub order.)
+    if (o.mode == CHL_MODE_BATCHED && B.poff && B.pbound > 0 && !small && o.hybrid_psi == 0) {
+        int64_t tot = 0;
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(&tot, B.poff + n, 8, hipMemcpyDeviceToHost));
+        uint64_t* byd = A.get<uint64_t>((size_t)std::max<int64_t>(1, tot));
+        if (!byd) return CHL_ERR_OOM;
+        if (launch_swap_halves(B.plab, byd, (uint64_t)tot, st)) return CHL_ERR_HIP;
+        if (launch_segsort_u64(byd, B.poff, n, tot, nullptr, st)) return CHL_ERR_HIP;
+        B.plab = byd;
+        B.dmaj = 1;
+    }
     S.small_trees = small ? small_capacity(B.key_bits) : 0;
     S.tune_ms = tune_ms;
     S.roots_in_flight = k;

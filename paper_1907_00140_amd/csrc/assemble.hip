@@ -170,6 +170,20 @@ int launch_group_min(const Pool& pool, uint64_t from, uint64_t to, uint32_t* pmi
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+__global__ void k_swap_halves(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t total) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t x = in[i];
+        out[i] = (x << 32) | (x >> 32);
+    }
+}
+
+int launch_swap_halves(const uint64_t* in, uint64_t* out, uint64_t total, hipStream_t st) {
+    if (!total) return 0;
+    hipLaunchKernelGGL(k_swap_halves, dim3(g(total)), dim3(256), 0, st, in, out, total);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st) {
     hipLaunchKernelGGL(k_old_sizes, dim3(g(n)), dim3(256), 0, st, n, off, count);
     return hipGetLastError() == hipSuccess ? 0 : -1;

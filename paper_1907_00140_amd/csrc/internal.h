@@ -91,6 +91,9 @@ struct TreeParams {
     // prefix hub from root h to v is at least (h's smallest prefix distance)
     // + pmin[v], so a candidate below that bound skips reading v's group
     const uint32_t* pmin;
+    // 1: plab entries are (dist << 32) | hub and each group is sorted by
+    // distance (the batched kernel's main phase); 0: (hub << 32) | dist
+    int32_t dmaj;
     // 1 for the combined graph of a directed build (the graph's vertices at
     // even rank positions 2i, their reversed copies at 2i + 1): a root's
     // distances to the prefix hubs are those of its partner h ^ 1 from the
@@ -205,6 +208,8 @@ int launch_prefix_extend(int32_t n, const Pool& pool, uint64_t from, uint64_t us
 // [from, to) of v (pmin starts all ones and only decreases, so it stays a
 // lower bound of v's group when entries leave it)
 int launch_group_min(const Pool& pool, uint64_t from, uint64_t to, uint32_t* pmin, hipStream_t st);
+// assemble.hip: out[i] = in[i] with its two 32-bit halves exchanged
+int launch_swap_halves(const uint64_t* in, uint64_t* out, uint64_t total, hipStream_t st);
 // assemble.hip: count[v] = size of v's group in off (0 for every v when
 // off is NULL): the running sizes that launch_prefix_extend continues from
 int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st);

@@ -167,7 +167,7 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                                             const int64_t* poff, const uint64_t* plab, uint32_t pbound,
                                             const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs,
                                             bool rank_query = false, const uint32_t* pmin = nullptr,
-                                            uint32_t dhmin = 0) {
+                                            uint32_t dhmin = 0, bool dmaj = false) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -245,11 +245,14 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                     for (int z = 0; z < 8; z++) lx[z] = i + z < le ? plab[i + z] : ~0ull;
 #pragma unroll
                     for (int z = 0; z < 8; z++) {
-                        const uint32_t x = (uint32_t)(lx[z] >> 32);
+                        const uint32_t x = dmaj ? (uint32_t)lx[z] : (uint32_t)(lx[z] >> 32);
+                        const uint32_t dd = dmaj ? (uint32_t)(lx[z] >> 32) : (uint32_t)lx[z];
                         if (x >= pbound) continue;
                         const uint32_t a = dh[x];
-                        if (a != 0xFFFFFFFFu && (uint64_t)a + (uint32_t)lx[z] <= nd) cand = false;
+                        if (a != 0xFFFFFFFFu && (uint64_t)a + dd <= nd) cand = false;
                     }
+                    // groups ordered by distance: no later entry is closer
+                    if (dmaj && (uint64_t)(uint32_t)(lx[7] >> 32) + dhmin > nd) break;
                 }
             }
             K old = seen[j];
@@ -400,10 +403,11 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         if (prune)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
-                const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                const uint32_t x = p.dmaj ? (uint32_t)lx : (uint32_t)(lx >> 32), y = x ^ px;
+                const uint32_t dd = p.dmaj ? (uint32_t)(lx >> 32) : (uint32_t)lx;
                 if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
-                    dh[y] = (uint32_t)lx;
-                    atomicMin(&S.dhmin, (uint32_t)lx);
+                    dh[y] = dd;
+                    atomicMin(&S.dhmin, dd);
                 }
             }
 
@@ -446,7 +450,7 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
                                            &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, p.poff,
                                            p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, HYB,
-                                           p.pmin, S.dhmin);
+                                           p.pmin, S.dhmin, p.dmaj != 0);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
@@ -572,7 +576,7 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         // every read of dh is behind the emission's barriers
         if (prune)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
-                const uint32_t x = (uint32_t)(p.plab[i] >> 32), y = x ^ px;
+                const uint32_t x = p.dmaj ? (uint32_t)p.plab[i] : (uint32_t)(p.plab[i] >> 32), y = x ^ px;
                 if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = 0xFFFFFFFFu;
             }
         __syncthreads();
