@@ -182,6 +182,7 @@ struct Build {
     const uint64_t* plab = nullptr;
     uint32_t* pmin = nullptr;            // lower bound of each vertex's group distances
     int32_t dmaj = 0;                    // plab entries (dist << 32) | hub, groups by distance (TreeParams::dmaj)
+    const uint64_t* plab_hub = nullptr;  // the same groups in hub order, (hub << 32) | dist
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
     int32_t partner = 0;                 // combined graph of a directed build (TreeParams::partner)
     unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
@@ -697,6 +698,8 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     HIPCHK(hipMemsetAsync(B.pmin, 0xFF, (size_t)n * 4, st));
     uint64_t* plab[2] = {nullptr, nullptr};
     size_t plab_cap[2] = {0, 0};
+    uint64_t* byd = nullptr;            // the groups ordered by distance
+    size_t byd_cap = 0;
     int cur = -1;                       // buffer holding the groups so far
     unsigned long long grouped = 0;     // pool entries grouped so far
     // trees in flight and workgroup size of the levels: 512 and 1024
@@ -725,7 +728,23 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
         grouped = used;
         B.poff = poff[cur];
         B.plab = plab[cur];
+        B.plab_hub = plab[cur];
+        B.dmaj = 0;
         B.cursor_base = used;
+        // the kernels read the groups ordered by distance (a pruning test
+        // stops at the first entry that cannot give a shorter walk); the
+        // groups in hub order stay for the next extension
+        if (used > byd_cap) {
+            if (byd) A.drop(byd);
+            byd_cap = std::max<size_t>(used, 2 * byd_cap);
+            byd = A.get<uint64_t>(byd_cap);
+            if (!byd) return CHL_ERR_OOM;
+        }
+        if (launch_swap_halves(plab[cur], byd, used, st) ||
+            launch_segsort_u64(byd, poff[cur], n, (int64_t)used, nullptr, st))
+            return CHL_ERR_HIP;
+        B.plab = byd;
+        B.dmaj = 1;
         return 0;
     };
     // level 0
@@ -1219,24 +1238,17 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     int64_t delta = 0;
     double tune_ms = 0;
     bool small = false;
+    // The pruning levels leave the groups ordered by distance (B.dmaj), as
+    // the batched, team and group kernels read them: a candidate's pruning
+    // test stops at the first entry whose distance, plus the root's nearest
+    // prefix hub, exceeds the candidate (no later entry can give a shorter
+    // walk). R-MAT 20: main phase 41.4 -> 32.7 ms. The small-tree kernel and
+    // the Hybrid read the groups in hub order, and so does the tuner's probe
+    // of the small-tree kernel.
+    const uint64_t* plab_byd = B.dmaj ? B.plab : nullptr;
+    if (B.dmaj) { B.plab = B.plab_hub; B.dmaj = 0; }
     if (int r = pick_params(A, B, g, o, st, k, wg, delta, small, tune_ms)) return r;
-    // The main phase reads the prefix groups ordered by distance: a
-    // candidate's pruning test then stops at the first entry whose distance,
-    // plus the root's nearest prefix hub, exceeds the candidate (no later
-    // entry can give a shorter walk). R-MAT 20: main phase 41.4 -> 32.7 ms
-    // for a 1.8 ms sort of 48 M entries. (The small-tree kernel and the
-    // Hybrid read the groups in hub order.)
-    if (o.mode == CHL_MODE_BATCHED && B.poff && B.pbound > 0 && !small && o.hybrid_psi == 0) {
-        int64_t tot = 0;
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(&tot, B.poff + n, 8, hipMemcpyDeviceToHost));
-        uint64_t* byd = A.get<uint64_t>((size_t)std::max<int64_t>(1, tot));
-        if (!byd) return CHL_ERR_OOM;
-        if (launch_swap_halves(B.plab, byd, (uint64_t)tot, st)) return CHL_ERR_HIP;
-        if (launch_segsort_u64(byd, B.poff, n, tot, nullptr, st)) return CHL_ERR_HIP;
-        B.plab = byd;
-        B.dmaj = 1;
-    }
+    if (plab_byd && !small && o.hybrid_psi == 0) { B.plab = plab_byd; B.dmaj = 1; }
     S.small_trees = small ? small_capacity(B.key_bits) : 0;
     S.tune_ms = tune_ms;
     S.roots_in_flight = k;

@@ -898,10 +898,11 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
             const int32_t hg = h ^ (int32_t)px;      // whose prefix labels give d(h, x)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
-                const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                const uint32_t x = p.dmaj ? (uint32_t)lx : (uint32_t)(lx >> 32), y = x ^ px;
+                const uint32_t dd = p.dmaj ? (uint32_t)(lx >> 32) : (uint32_t)lx;
                 if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
-                    dh[y] = (uint32_t)lx;
-                    atomicMin(&S.dhmin, (uint32_t)lx);
+                    dh[y] = dd;
+                    atomicMin(&S.dhmin, dd);
                 }
             }
             __syncthreads();
@@ -960,7 +961,7 @@ __global__ __launch_bounds__(WG) void k_tree_team(TreeParams p, int W, long long
                                            (ull*)&tw[T_CNT0 + (it + 1) % 3], (ull*)&tw[T_FAR],
                                            (ull*)&tw[T_FARCLEAN], (ull*)&tw[T_UMAX], p.poff, p.plab,
                                            (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, false,
-                                           p.pmin, S.dhmin);
+                                           p.pmin, S.dhmin, p.dmaj != 0);
                 if (leader) {
                     tws(tw, T_CNT0 + (it + 2) % 3, 0);
                     tws(tw, T_SETTLED, twl<long long>(tw, T_SETTLED) + ncur);
@@ -1608,11 +1609,14 @@ __device__ __forceinline__ void group_relax(const TreeParams& p, const GroupCtx<
                     for (int z = 0; z < 4; z++) lx[z] = i + z < le ? p.plab[i + z] : ~0ull;
 #pragma unroll
                     for (int z = 0; z < 4; z++) {
-                        const uint32_t x = (uint32_t)(lx[z] >> 32);
+                        const uint32_t x = p.dmaj ? (uint32_t)lx[z] : (uint32_t)(lx[z] >> 32);
+                        const uint32_t dd = p.dmaj ? (uint32_t)(lx[z] >> 32) : (uint32_t)lx[z];
                         if (x >= cx.pb) continue;
                         const uint32_t ax = dhb[x];
-                        if (ax != 0xFFFFFFFFu && (uint64_t)ax + (uint32_t)lx[z] <= nd) cand = false;
+                        if (ax != 0xFFFFFFFFu && (uint64_t)ax + dd <= nd) cand = false;
                     }
+                    // groups ordered by distance: no later entry is closer
+                    if (p.dmaj && (uint64_t)(uint32_t)(lx[3] >> 32) + S.dhmin[b] > nd) break;
                 }
             }
             K old = seen[j];
@@ -1731,10 +1735,11 @@ __global__ __launch_bounds__(WG) void k_tree_group(TreeParams p, int W, long lon
                 const int32_t hg = h ^ (int32_t)px;
                 for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                     const uint64_t lx = p.plab[i];
-                    const uint32_t x = (uint32_t)(lx >> 32), y = x ^ px;
+                    const uint32_t x = p.dmaj ? (uint32_t)lx : (uint32_t)(lx >> 32), y = x ^ px;
+                    const uint32_t dd = p.dmaj ? (uint32_t)(lx >> 32) : (uint32_t)lx;
                     if (x < pb && y < pb) {
-                        dh[b * pb + y] = (uint32_t)lx;
-                        atomicMin(&S.dhmin[b], (uint32_t)lx);
+                        dh[b * pb + y] = dd;
+                        atomicMin(&S.dhmin[b], dd);
                     }
                 }
             }
