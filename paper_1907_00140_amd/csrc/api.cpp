@@ -1023,7 +1023,7 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
     // [0, B.cursor_base)) and the PLaNT windows' entries after them
     unsigned long long grouped = B.last_used;
     const unsigned long long lev = B.poff ? B.cursor_base : 0;
-    if (int r = extend(B.poff, B.plab, lev, grouped, 0)) return r;
+    if (int r = extend(B.poff, B.dmaj ? B.plab_hub : B.plab, lev, grouped, 0)) return r;
     if (!B.pmin) {
         B.pmin = A.get<uint32_t>(n);
         if (!B.pmin) return CHL_ERR_OOM;
@@ -1036,10 +1036,24 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
     int64_t x = std::max<int64_t>(64, 2 * (int64_t)s.k);
     HostCtl* hc = host_ctl();
     if (!hc) return CHL_ERR_HIP;
+    // the pruned trees read the groups ordered by distance, as the other
+    // trees do; the groups in hub order serve the extensions and the cleaning
+    uint64_t* byd = nullptr;
+    size_t byd_cap = 0;
     while (lo < n) {
         const int32_t hi = (int32_t)std::min<int64_t>(n, (int64_t)lo + x);
+        if (grouped > byd_cap) {
+            if (byd) A.drop(byd);
+            byd_cap = std::max<size_t>(grouped, 2 * byd_cap);
+            byd = A.get<uint64_t>(byd_cap);
+            if (!byd) return CHL_ERR_OOM;
+        }
+        if (launch_swap_halves(tlab[cur], byd, grouped, st) ||
+            launch_segsort_u64(byd, toff[cur], n, (int64_t)grouped, nullptr, st))
+            return CHL_ERR_HIP;
         B.poff = toff[cur];
-        B.plab = tlab[cur];
+        B.plab = byd;
+        B.dmaj = 1;
         B.pbound = lo;
         if (int r = run_batched(A, B, s, wg, delta, o.early_term, nullptr, hi - lo, st, launches, 3, lo)) return r;
         const unsigned long long used = B.last_used;
@@ -1095,6 +1109,7 @@ static int run_hybrid(Arena& A, Build& B, const chl_build_opts& o, const Slots& 
     B.rlab = nullptr;
     B.poff = toff[cur];
     B.plab = tlab[cur];
+    B.dmaj = 0;
     if (own_stats) { A.drop(own_stats); B.stats = nullptr; }
     return 0;
 }
@@ -1242,13 +1257,12 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     // the batched, team and group kernels read them: a candidate's pruning
     // test stops at the first entry whose distance, plus the root's nearest
     // prefix hub, exceeds the candidate (no later entry can give a shorter
-    // walk). R-MAT 20: main phase 41.4 -> 32.7 ms. The small-tree kernel and
-    // the Hybrid read the groups in hub order, and so does the tuner's probe
-    // of the small-tree kernel.
+    // walk). R-MAT 20: main phase 41.4 -> 32.7 ms. The small-tree kernel
+    // reads the groups in hub order, and so does the tuner's probe of it.
     const uint64_t* plab_byd = B.dmaj ? B.plab : nullptr;
     if (B.dmaj) { B.plab = B.plab_hub; B.dmaj = 0; }
     if (int r = pick_params(A, B, g, o, st, k, wg, delta, small, tune_ms)) return r;
-    if (plab_byd && !small && o.hybrid_psi == 0) { B.plab = plab_byd; B.dmaj = 1; }
+    if (plab_byd && !small) { B.plab = plab_byd; B.dmaj = 1; }
     S.small_trees = small ? small_capacity(B.key_bits) : 0;
     S.tune_ms = tune_ms;
     S.roots_in_flight = k;
