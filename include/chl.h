@@ -124,11 +124,11 @@ typedef struct chl_build_opts {
                                 level whose roots emitted >= 2^21 labels -- is
                                 pruned by the labels of the hubs [0, g)
                                 (complete by then), up to a prefix of
-                                prune_hubs hubs (<= 4096); every other tree is
+                                prune_hubs hubs (<= 8192); every other tree is
                                 pruned by that prefix. A relaxation is dropped
                                 when a walk through a prefix hub is no longer.
                                 Same labels either way. > 0: that prefix size;
-                                0: min(4096, max(64, n/64)), kept only if the
+                                0: min(8192, max(64, n/64)), kept only if the
                                 16-hub level halves the work of a probe of
                                 later trees (decided once per graph and
                                 ranking, cached; always kept when autotune is

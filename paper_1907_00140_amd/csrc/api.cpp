@@ -681,11 +681,12 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
                       int& launches, int32_t& grown) {
     const int32_t n = B.n;
     const double wm = 0.5 * (1.0 + B.maxw);
-    // default prefix: n/64 hubs, at least 64, at most 4096: each level
+    // default prefix: n/64 hubs, at least 64, at most 8192: each level
     // adds latency, each prefix hub saves work in every later tree, and
     // there are more later trees on larger graphs (R-MAT 16: 1024 hubs
     // build 4% faster than 4096; R-MAT 20: 4096 run the main phase 2.8x
-    // faster than 2048)
+    // faster than 2048, and 8192 in 18.2 ms instead of 32.7, for a last
+    // level [2048, 8192) of 9.4 ms instead of [2048, 4096) of 3.7)
     const int32_t gdef = std::min<int32_t>(MAX_PREFIX, std::max<int32_t>(64, n / 64));
     const int32_t gmax = std::min<int32_t>(o.prune_hubs > 0 ? o.prune_hubs : gdef, n / 2);
     // prefix labels grouped by vertex, double-buffered: each level's

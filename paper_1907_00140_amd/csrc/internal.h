@@ -237,7 +237,7 @@ int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partn
 // assemble.hip: totals of the per-root statistics (settled, arcs, stopped
 // early) into sums[0..2] (zeroed by the caller)
 int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);
-constexpr int MAX_PREFIX = 4096;   // largest pruning prefix (root distances live in LDS)
+constexpr int MAX_PREFIX = 8192;   // largest pruning prefix (root distances live in LDS, 32 KB)
 
 // query.hip: d(u, v) from the lists of u in (off_u, hub_u, dist_u) and of v
 // in (off_v, hub_v, dist_v) (the same arrays for an undirected labeling;

@@ -22,7 +22,7 @@ counts the schedule that the library's default build takes (the policy below
 mirrors the library's: roots [0, 16) first, then each level 8 times the
 prefix, or 2 times after a level whose roots emitted 2^21 labels or more, or
 4 times for the first pruned level of a directed build's combined graph, up
-to min(4096, max(64, n/64), n/2) hubs). Directed workloads are counted on
+to min(8192, max(64, n/64), n/2) hubs). Directed workloads are counted on
 their combined graph (the graph and its reversal, ranks interleaved), as the
 library builds them.
 """
@@ -67,7 +67,7 @@ def level_bounds(labels_per_root, gmax, first=None):
 
 
 def default_prefix(n):
-    return min(4096, max(64, n // 64), n // 2)
+    return min(8192, max(64, n // 64), n // 2)
 
 
 def _sums(st, lo, hi):
