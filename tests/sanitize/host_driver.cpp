@@ -51,7 +51,8 @@ int main() {
         {"k", [](chl_build_opts& x) { x.roots_in_flight = -2; }},
         {"stride", [](chl_build_opts& x) { x.root_count = 2; x.root_stride = 0; }},
         {"range", [](chl_build_opts& x) { x.root_count = 2; x.root_stride = 5; }},
-        {"prefix", [](chl_build_opts& x) { x.prune_hubs = 5000; }},
+        {"prefix", [](chl_build_opts& x) { x.prune_hubs = 8193; }},
+        {"hybrid", [](chl_build_opts& x) { x.hybrid_psi = -1; }},
         {"team", [](chl_build_opts& x) { x.team_wgs = 17; }},
     };
     for (auto& b : bad_opts) {
