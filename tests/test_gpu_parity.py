@@ -261,7 +261,7 @@ def test_invalid_inputs():
         assert e.value.code == -1
     # options out of range
     for kw in (dict(wg_size=96), dict(mode="plain", wg_size=64), dict(mode="plain", wg_size=1024),
-               dict(team_wgs=17), dict(team_wgs=-1), dict(prune_hubs=5000), dict(roots_in_flight=-2)):
+               dict(team_wgs=17), dict(team_wgs=-1), dict(prune_hubs=8193), dict(roots_in_flight=-2)):
         with pytest.raises(chl.ChlError) as e:
             chl.build(row, col, w, order, **kw)
         assert e.value.code == -1, kw
