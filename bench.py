@@ -16,11 +16,12 @@ scans, appear only in separately named fields.
 The same run also measures the other workloads (64x64 grid, R-MAT 16,
 1024x1024 grid with shortcuts), the full serving experiment (labelings of
 R-MAT 16 and the large grid resident, 10^7 Poisson queries at three rates,
-twice each, 16 build requests), directed R-MAT 16, shortest paths, the
-plain one-root-per-launch form, an atomic-minimum ceiling and the CPU oracle.
+twice each, 16 build requests), directed R-MAT 16, the Hybrid construction
+against PLaNT trees alone, shortest paths, the plain one-root-per-launch form,
+an atomic-minimum reference and the CPU oracle.
 
 Prints one JSON line. Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--sections headline,workloads,serving,directed,paths,atomics,cpu]
+       [--sections headline,workloads,serving,directed,hybrid,paths,atomics,cpu]
 """
 from __future__ import annotations
 
