@@ -183,6 +183,7 @@ struct Build {
     uint32_t* pmin = nullptr;            // lower bound of each vertex's group distances
     int32_t dmaj = 0;                    // plab entries (dist << 32) | hub, groups by distance (TreeParams::dmaj)
     const uint64_t* plab_hub = nullptr;  // the same groups in hub order, (hub << 32) | dist
+    int32_t hashdh = 0;                  // main phase: root distances hashed (TreeParams::hashdh)
     int32_t pbound = 0;                  // prune with the hubs [0, pbound)
     int32_t partner = 0;                 // combined graph of a directed build (TreeParams::partner)
     unsigned long long cursor_base = 0;  // pool entries kept before the main tree phase
@@ -281,6 +282,9 @@ TreeParams params(Build& B, const Slots& s, int64_t delta, int early, const int3
     p.plab = B.plab;
     p.pmin = B.pmin;
     p.dmaj = B.dmaj;
+    p.hashdh = B.hashdh;
+    p.ovf = B.far2;
+    p.novf = B.ctl32 + 5;
     p.pbound = B.pbound;
     p.partner = B.partner;
     p.dhg = B.dhg;
@@ -354,7 +358,9 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
                 int phase = 0, int32_t root_base = 0, const TeamCfg* team = nullptr,
                 bool roots_in_place = false, const GroupCfg* grp = nullptr, int small_wgs = 0) {
     std::vector<int32_t> pending;
-    std::vector<int32_t> overflow;      // roots the small kernel gave up (grown afterwards)
+    std::vector<int32_t> overflow;      // roots the small or hashed kernel gave up (grown afterwards)
+    // main phase and its probes with the root's prefix distances hashed
+    const bool hs = B.hashdh && B.poff && B.pbound > 0 && (phase == 0 || phase == 1) && !team && !grp && !small_wgs;
     const int32_t* dev_roots = nullptr;
     if (roots_host) {
         HIPCHK(hipMemcpyAsync(B.roots, roots_host, (size_t)nroots * 4, hipMemcpyHostToDevice, st));
@@ -403,7 +409,7 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
         B.last_used = c64[0];
         if (c32[3] & ERR_BIT_INVALID) return CHL_ERR_INVALID_ARG;
         if (c32[3] & ERR_BIT_TEAM) return CHL_ERR_HIP;
-        if (small_wgs && c32[5] > 0) {
+        if ((small_wgs || hs) && c32[5] > 0) {
             const size_t no = overflow.size();
             overflow.resize(no + (size_t)std::min(c32[5], B.n));
             HIPCHK(hipMemcpy(overflow.data() + no, B.far2, (overflow.size() - no) * 4, hipMemcpyDeviceToHost));
@@ -447,7 +453,12 @@ int run_batched(Arena& A, Build& B, const Slots& s, int wg, int64_t delta, int e
     }
     if (!overflow.empty()) {
         std::sort(overflow.begin(), overflow.end());   // rank order
-        return run_batched(A, B, s, wg, delta, early, overflow.data(), (int32_t)overflow.size(), st, launches, phase);
+        const int32_t hsave = B.hashdh;
+        B.hashdh = 0;                                  // the dense array for these roots
+        const int r = run_batched(A, B, s, wg, delta, early, overflow.data(), (int32_t)overflow.size(), st, launches,
+                                  phase);
+        B.hashdh = hsave;
+        return r;
     }
     return 0;
 }
@@ -1262,6 +1273,9 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     // reads the groups in hub order, and so does the tuner's probe of it.
     const uint64_t* plab_byd = B.dmaj ? B.plab : nullptr;
     if (B.dmaj) { B.plab = B.plab_hub; B.dmaj = 0; }
+    // a large prefix: the main phase hashes each root's prefix distances in
+    // LDS (more workgroups resident than with a dense prefix-size array)
+    B.hashdh = B.pbound >= HASH_MIN_PREFIX ? 1 : 0;
     if (int r = pick_params(A, B, g, o, st, k, wg, delta, small, tune_ms)) return r;
     if (plab_byd && !small) { B.plab = plab_byd; B.dmaj = 1; }
     S.small_trees = small ? small_capacity(B.key_bits) : 0;

@@ -94,6 +94,13 @@ struct TreeParams {
     // 1: plab entries are (dist << 32) | hub and each group is sorted by
     // distance (the batched kernel's main phase); 0: (hub << 32) | dist
     int32_t dmaj;
+    // batched form, main phase and its probes: 1 = the root's prefix
+    // distances in a small LDS hash instead of a dense LDS array (more
+    // workgroups resident); a root with more than HASH_MAX_LABELS prefix
+    // labels is not grown but appended to ovf (count *novf), for a dense run
+    int32_t hashdh;
+    int32_t* ovf;
+    int32_t* novf;
     // 1 for the combined graph of a directed build (the graph's vertices at
     // even rank positions 2i, their reversed copies at 2i + 1): a root's
     // distances to the prefix hubs are those of its partner h ^ 1 from the
@@ -237,6 +244,8 @@ int launch_level_order(const int64_t* poff, int32_t g, int32_t g2, int32_t partn
 // assemble.hip: totals of the per-root statistics (settled, arcs, stopped
 // early) into sums[0..2] (zeroed by the caller)
 int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t st);
+constexpr int HASH_MIN_PREFIX = 4096;   // prefixes from this size hash the root's distances
+constexpr int HASH_MAX_LABELS = 512;    // prefix labels of a root that the hash holds
 constexpr int MAX_PREFIX = 8192;   // largest pruning prefix (root distances live in LDS, 32 KB)
 
 // query.hip: d(u, v) from the lists of u in (off_u, hub_u, dist_u) and of v

@@ -157,6 +157,32 @@ struct Expand {
 // are counted in *cnt_far_clean.
 constexpr int RELAX_ILP = 4;
 
+// The root's distances to its prefix hubs as an open-addressing LDS hash
+// (keys -1 when free, at most half full): the main phase's roots have a few
+// dozen prefix labels, and a dense array of prefix-size words limits how
+// many workgroups a compute unit holds.
+constexpr int HCAP = 2 * HASH_MAX_LABELS;
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t x) {
+    return (x * 2654435761u) >> (32 - __builtin_ctz((uint32_t)HCAP));
+}
+
+__device__ __forceinline__ uint32_t hash_lookup(const int32_t* hk, const uint32_t* hv, uint32_t x) {
+    uint32_t s = hash_slot(x);
+    for (int i = 0; i < HCAP; i++, s = (s + 1) & (HCAP - 1)) {
+        const int32_t k = hk[s];
+        if (k == (int32_t)x) return hv[s];
+        if (k < 0) return 0xFFFFFFFFu;
+    }
+    return 0xFFFFFFFFu;
+}
+
+template <int C>
+struct HashLds {
+    int32_t k[C];
+    uint32_t v[C];
+};
+
 template <typename K, int WG, int SCOPE, typename C>
 __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* flags,
                                             const int32_t* cur, int32_t base, int32_t nv,
@@ -167,7 +193,8 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                                             const int64_t* poff, const uint64_t* plab, uint32_t pbound,
                                             const uint32_t* dh, Expand<K, WG>& X, uint64_t& arcs,
                                             bool rank_query = false, const uint32_t* pmin = nullptr,
-                                            uint32_t dhmin = 0, bool dmaj = false) {
+                                            uint32_t dhmin = 0, bool dmaj = false,
+                                            const int32_t* hk = nullptr) {
     const int tid = threadIdx.x;
     uint32_t deg = 0;
     if (tid < nv) {
@@ -248,7 +275,7 @@ __device__ __forceinline__ void relax_block(const RGraph& g, K* key, uint32_t* f
                         const uint32_t x = dmaj ? (uint32_t)lx[z] : (uint32_t)(lx[z] >> 32);
                         const uint32_t dd = dmaj ? (uint32_t)(lx[z] >> 32) : (uint32_t)lx[z];
                         if (x >= pbound) continue;
-                        const uint32_t a = dh[x];
+                        const uint32_t a = hk ? hash_lookup(hk, dh, x) : dh[x];
                         if (a != 0xFFFFFFFFu && (uint64_t)a + dd <= nd) cand = false;
                     }
                     // groups ordered by distance: no later entry is closer
@@ -349,15 +376,16 @@ __device__ __forceinline__ bool may_stop(BatchedLds<K, WG>& S, const K* key, con
 // tree's pool range recorded in p.rlab for the cleaning that follows.
 // PRUNE: rank-prefix pruning with p.poff / p.plab; the root's distances to
 // the prefix hubs live in dynamic LDS (p.pbound words) below phase 3.
-template <typename K, int WG, int PHASE, bool PRUNE>
+template <typename K, int WG, int PHASE, bool PRUNE, bool HS>
 __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     constexpr int SC = __HIP_MEMORY_SCOPE_WORKGROUP;
     constexpr bool HYB = PHASE == 3;
     __shared__ BatchedLds<K, WG> S;
+    __shared__ HashLds<HS ? HCAP : 1> H;
     extern __shared__ uint32_t dh_lds[];
     const int tid = threadIdx.x;
     const int64_t slot = blockIdx.x;
-    uint32_t* dh = HYB ? p.dhg + slot * p.s.stride : dh_lds;
+    uint32_t* dh = HYB ? p.dhg + slot * p.s.stride : HS ? H.v : dh_lds;
     K* key = (K*)p.s.key + slot * p.s.stride;
     uint32_t* flags = p.s.flags + slot * p.s.fstride;
     int32_t* touched = p.s.touched + slot * p.s.stride;
@@ -367,8 +395,10 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
     // dh is all ones between trees: a tree sets its root's entries and
     // clears them when it is done (the global array of phase 3 is set to
     // all ones when it is allocated)
-    if (PRUNE && !HYB)
+    if (PRUNE && !HYB && !HS)
         for (int x = tid; x < p.pbound; x += WG) dh[x] = 0xFFFFFFFFu;
+    if (HS)
+        for (int x = tid; x < HCAP; x += WG) H.k[x] = -1;
     if (tid == 0) { S.bnext = 0; S.bend = 0; }
 
     for (;;) {
@@ -400,13 +430,26 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
         const bool prune = PRUNE && h >= p.pbound;
         const uint32_t px = (uint32_t)p.partner;
         const int32_t hg = h ^ (int32_t)px;          // whose prefix labels give d(h, x)
+        if (HS && prune && p.poff[hg + 1] - p.poff[hg] > HASH_MAX_LABELS) {
+            // more prefix labels than the hash holds: grown afterwards with
+            // the dense array (no emission, no statistics here)
+            if (tid == 0) p.ovf[atomicAdd(p.novf, 1)] = h;
+            __syncthreads();
+            continue;
+        }
         if (prune)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint64_t lx = p.plab[i];
                 const uint32_t x = p.dmaj ? (uint32_t)lx : (uint32_t)(lx >> 32), y = x ^ px;
                 const uint32_t dd = p.dmaj ? (uint32_t)(lx >> 32) : (uint32_t)lx;
                 if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) {
-                    dh[y] = dd;
+                    if (HS) {
+                        uint32_t s = hash_slot(y);
+                        while (atomicCAS(&H.k[s], -1, (int32_t)y) != -1) s = (s + 1) & (HCAP - 1);
+                        H.v[s] = dd;
+                    } else {
+                        dh[y] = dd;
+                    }
                     atomicMin(&S.dhmin, dd);
                 }
             }
@@ -450,7 +493,7 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
                                            nextbit, h, T, touched, next, far, &S.cnt_touched,
                                            &S.cnt_next, &S.cnt_far, &S.far_clean, &S.umax, p.poff,
                                            p.plab, (uint32_t)p.pbound, prune ? dh : nullptr, S.X, arcs, HYB,
-                                           p.pmin, S.dhmin, p.dmaj != 0);
+                                           p.pmin, S.dhmin, p.dmaj != 0, HS ? H.k : nullptr);
                 __syncthreads();
                 it++;
                 if (tid == 0) { S.ncur = S.cnt_next; S.cnt_next = 0; }
@@ -574,7 +617,9 @@ __global__ __launch_bounds__(WG) void k_tree_batched(TreeParams p) {
             s[4] = it; s[5] = (int64_t)(__builtin_amdgcn_s_memrealtime() - t_start);
         }
         // every read of dh is behind the emission's barriers
-        if (prune)
+        if (HS && prune)
+            for (int x = tid; x < HCAP; x += WG) H.k[x] = -1;
+        if (prune && !HS)
             for (int64_t i = p.poff[hg] + tid; i < p.poff[hg + 1]; i += WG) {
                 const uint32_t x = p.dmaj ? (uint32_t)p.plab[i] : (uint32_t)(p.plab[i] >> 32), y = x ^ px;
                 if (x < (uint32_t)p.pbound && y < (uint32_t)p.pbound) dh[y] = 0xFFFFFFFFu;
@@ -2026,15 +2071,18 @@ int launch_batched_t(const TreeParams& p, int phase, hipStream_t st) {
     const bool pr = p.poff != nullptr && p.pbound > 0;
     const size_t dl = pr ? (size_t)p.pbound * 4 : 0;
     const dim3 g(p.s.k), b(WG);
+    const bool hs = pr && p.hashdh && p.ovf && p.novf;
     if (phase == 3) {
         if (!pr || !p.dhg || !p.rlab) return -1;
-        hipLaunchKernelGGL((k_tree_batched<K, WG, 3, true>), g, b, 0, st, p);
-    } else if (phase == 1 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true>), g, b, dl, st, p);
-    else if (phase == 1) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, false>), g, b, 0, st, p);
-    else if (phase == 2 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, true>), g, b, dl, st, p);
-    else if (phase == 2) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, false>), g, b, 0, st, p);
-    else if (pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 0, true>), g, b, dl, st, p);
-    else hipLaunchKernelGGL((k_tree_batched<K, WG, 0, false>), g, b, 0, st, p);
+        hipLaunchKernelGGL((k_tree_batched<K, WG, 3, true, false>), g, b, 0, st, p);
+    } else if (phase == 1 && hs) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true, true>), g, b, 0, st, p);
+    else if (phase == 1 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, true, false>), g, b, dl, st, p);
+    else if (phase == 1) hipLaunchKernelGGL((k_tree_batched<K, WG, 1, false, false>), g, b, 0, st, p);
+    else if (phase == 2 && pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, true, false>), g, b, dl, st, p);
+    else if (phase == 2) hipLaunchKernelGGL((k_tree_batched<K, WG, 2, false, false>), g, b, 0, st, p);
+    else if (hs) hipLaunchKernelGGL((k_tree_batched<K, WG, 0, true, true>), g, b, 0, st, p);
+    else if (pr) hipLaunchKernelGGL((k_tree_batched<K, WG, 0, true, false>), g, b, dl, st, p);
+    else hipLaunchKernelGGL((k_tree_batched<K, WG, 0, false, false>), g, b, 0, st, p);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -481,3 +481,21 @@ def test_sort_tiers_two_hubs():
     assert_same_labels(off, hub, dist, ref)
     pairs = np.stack([g.integers(0, n, 20000), g.integers(0, n, 20000)], 1).astype(np.int32)
     assert np.array_equal(L.query(pairs).cpu().numpy(), oracle.query(ref, pairs))
+
+
+@pytest.mark.parametrize("rank", ["degree", "random"])
+def test_hashed_root_distances(rank):
+    """Prefixes of 4096 hubs and more: the main phase holds each root's
+    prefix distances in an LDS hash; roots with more prefix labels than it
+    holds (most of them under a random ranking) are grown afterwards with the
+    dense array. Labels and labels per root equal the oracle's."""
+    c = gg.make_config("rmat14s11")
+    order = c["order"] if rank == "degree" else gg.random_rank(c["n"], 5)
+    _say("hashed root distances", rank)
+    ref = oracle.chl(c["row_ptr"], c["col"], c["w"], order)
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], order, prune_hubs=4096)
+    assert_same_labels(off, hub, dist, ref, "hashed " + rank)
+    st = L.stats(per_root=True)
+    assert st["prune_hubs"] == 4096
+    assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+    L.free()
