@@ -413,10 +413,8 @@ typedef struct chl_server_opts {
 
 void chl_server_opts_default(chl_server_opts* o);
 /* Create a server. alloc == NULL: builds allocate from the device's default
- * stream-ordered memory pool on their build streams; the server sets that
- * pool to keep up to mem_budget bytes and takes them from the driver here
- * (in 256 MB pieces, freed back to the pool), so that builds admitted later
- * do not map new memory while query batches run. alloc != NULL: builds (and
+ * stream-ordered memory pool on their build streams (nothing is reserved
+ * up front; the pool reuses memory that earlier builds freed). alloc != NULL: builds (and
  * the labelings they produce, released by chl_server_destroy) take device
  * memory from that allocator instead; it must be callable from the server's
  * threads and stay valid until chl_server_destroy returns (the server

@@ -392,18 +392,12 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
     auto* s = new chl_server();
     s->o = so;
     if (alloc) s->user = *alloc;
-    // builds allocate from the device's default stream-ordered pool: let it
-    // keep up to the build budget instead of returning memory to the driver
-    // at every synchronisation (a fresh driver allocation can stall the
-    // device, and with it the query batches)
-    {
-        int dev = 0;
-        hipMemPool_t pool;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t keep = so.mem_budget;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-        }
-    }
+    // Builds allocate from the device's default stream-ordered pool, which
+    // serves a build's temporaries from memory freed by earlier builds. No
+    // memory is reserved up front: the pool was measured to keep at most
+    // about 0.75 GB of freed memory whatever its release threshold, so
+    // taking the budget from the driver here and freeing it into the pool
+    // only moved it through the driver and back.
     bool ok = hipStreamCreateWithFlags(&s->qs, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; i < so.build_streams && ok; i++) {
         hipStream_t st;
@@ -432,21 +426,6 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
     if (!ok) {
         chl_server_destroy(s);
         return CHL_ERR_HIP;
-    }
-    // take the build budget from the driver now, in pieces, and hand it back
-    // to the pool, which keeps it (release threshold above): builds admitted
-    // later allocate from memory the pool already holds instead of mapping
-    // new memory while query batches run
-    if (!s->bs.empty() && !s->user.alloc) {
-        const size_t piece = (size_t)256 << 20;
-        std::vector<void*> held;
-        for (size_t got = 0; got + piece <= so.mem_budget; got += piece) {
-            void* p = nullptr;
-            if (hipMallocAsync(&p, piece, s->bs[0]) != hipSuccess || !p) break;
-            held.push_back(p);
-        }
-        for (void* p : held) (void)hipFreeAsync(p, s->bs[0]);
-        (void)hipStreamSynchronize(s->bs[0]);
     }
     *out = s;
     return CHL_OK;
