@@ -5,7 +5,8 @@
 //              partners 64 or more positions apart sit in the same lane,
 //              closer ones are exchanged with lane shuffles;
 //   <= LCAP    one 1024-thread block per segment, bitonic network in LDS;
-//   larger     one block per segment, bitonic network in global memory.
+//   larger     one 1024-thread block per segment, bitonic network in global
+//              memory.
 // A length that is not a power of two is padded with all-ones keys, which
 // sort to the end and are not stored. The LDS and global tiers use the form
 // of the network in which every comparator moves the smaller key to the lower
@@ -20,6 +21,7 @@ namespace {
 constexpr int LCAP = 8192;
 constexpr int BLK = 256;
 constexpr int BLKL = 1024;
+constexpr int BLKG = 1024;
 
 template <int E>
 __device__ __forceinline__ void wave_bitonic(uint64_t (&x)[E], int lane) {
@@ -63,18 +65,34 @@ __device__ __forceinline__ void wave_sort(uint64_t* __restrict__ a, int len, int
         if (e * 64 + lane < len) a[e * 64 + lane] = x[e];
 }
 
+// Segments are dealt out interleaved: with G workers (waves or blocks) of W
+// lanes each, worker w checks the segments w + G * (i * W + lane), i = 0, 1,
+// ..., so the lengths of W segments are read in one parallel step and the
+// long segments, which a rank order clusters at low ids, spread over workers.
 __global__ __launch_bounds__(BLK) void k_sort_wave(uint64_t* __restrict__ keys,
                                                    const int64_t* __restrict__ off, int64_t nseg) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * BLK + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * BLK) >> 6;
-    for (int64_t s = wave; s < nseg; s += nwaves) {
-        const int64_t b = off[s];
-        const int len = (int)(off[s + 1] - b);
-        if (len <= 1 || len > 256) continue;
-        if (len <= 64) wave_sort<1>(keys + b, len, lane);
-        else if (len <= 128) wave_sort<2>(keys + b, len, lane);
-        else wave_sort<4>(keys + b, len, lane);
+    for (int64_t i0 = 0; wave + nwaves * i0 < nseg; i0 += 64) {
+        const int64_t s = wave + nwaves * (i0 + lane);
+        int64_t b = 0;
+        int len = 0;
+        if (s < nseg) {
+            b = off[s];
+            const int64_t l = off[s + 1] - b;
+            len = l > 256 ? 257 : (int)l;
+        }
+        uint64_t m = __ballot(len > 1 && len <= 256);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int64_t sb = __shfl(b, src);
+            const int sl = __shfl(len, src);
+            if (sl <= 64) wave_sort<1>(keys + sb, sl, lane);
+            else if (sl <= 128) wave_sort<2>(keys + sb, sl, lane);
+            else wave_sort<4>(keys + sb, sl, lane);
+        }
     }
 }
 
@@ -86,72 +104,104 @@ __device__ __forceinline__ void cas(uint64_t* a, int i, int j) {
 __global__ __launch_bounds__(BLKL) void k_sort_lds(uint64_t* __restrict__ keys,
                                                    const int64_t* __restrict__ off, int64_t nseg) {
     __shared__ uint64_t a[LCAP];
-    for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-        const int64_t b = off[s];
-        const int len = (int)(off[s + 1] - b);
-        if (len <= 256 || len > LCAP) continue;
-        int lp = 9;
-        while ((1 << lp) < len) lp++;
-        const int p2 = 1 << lp;
-        for (int i = threadIdx.x; i < p2; i += BLKL) a[i] = i < len ? keys[b + i] : ~0ull;
+    __shared__ int64_t lst[BLKL];
+    __shared__ int cnt;
+    const int64_t G = gridDim.x;
+    for (int64_t i0 = 0; (int64_t)blockIdx.x + G * i0 < nseg; i0 += BLKL) {
+        if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
-        for (int lk = 1; lk <= lp; lk++) {
-            const int k = 1 << lk;
-            // mirrored step: pairs (i, i ^ (k - 1)) inside blocks of k
-            for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
-                const int i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
-                cas(a, i, i ^ (k - 1));
-            }
-            __syncthreads();
-            for (int lj = lk - 2; lj >= 0; lj--) {
-                const int j = 1 << lj;
-                for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
-                    const int i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
-                    cas(a, i, i + j);
-                }
-                __syncthreads();
+        {
+            const int64_t s = (int64_t)blockIdx.x + G * (i0 + threadIdx.x);
+            if (s < nseg) {
+                const int64_t l = off[s + 1] - off[s];
+                if (l > 256 && l <= LCAP) lst[atomicAdd(&cnt, 1)] = s;
             }
         }
-        for (int i = threadIdx.x; i < len; i += BLKL) keys[b + i] = a[i];
+        __syncthreads();
+        const int c = cnt;
+        for (int q = 0; q < c; q++) {
+            const int64_t s = lst[q];
+            const int64_t b = off[s];
+            const int len = (int)(off[s + 1] - b);
+            int lp = 9;
+            while ((1 << lp) < len) lp++;
+            const int p2 = 1 << lp;
+            for (int i = threadIdx.x; i < p2; i += BLKL) a[i] = i < len ? keys[b + i] : ~0ull;
+            __syncthreads();
+            for (int lk = 1; lk <= lp; lk++) {
+                const int k = 1 << lk;
+                // mirrored step: pairs (i, i ^ (k - 1)) inside blocks of k
+                for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
+                    const int i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
+                    cas(a, i, i ^ (k - 1));
+                }
+                __syncthreads();
+                for (int lj = lk - 2; lj >= 0; lj--) {
+                    const int j = 1 << lj;
+                    for (int t = threadIdx.x; t < p2 / 2; t += BLKL) {
+                        const int i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
+                        cas(a, i, i + j);
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = threadIdx.x; i < len; i += BLKL) keys[b + i] = a[i];
+            __syncthreads();
+        }
+        // every thread has read cnt and lst before the next round resets them
         __syncthreads();
     }
 }
 
-__global__ __launch_bounds__(BLK) void k_sort_global(uint64_t* __restrict__ keys,
-                                                     const int64_t* __restrict__ off, int64_t nseg) {
-    for (int64_t s = blockIdx.x; s < nseg; s += gridDim.x) {
-        const int64_t b = off[s];
-        const int64_t len = off[s + 1] - b;
-        if (len <= LCAP) continue;
-        uint64_t* a = keys + b;
-        int lp = 0;
-        while (((int64_t)1 << lp) < len) lp++;
-        const int64_t half = (int64_t)1 << (lp - 1);
-        for (int lk = 1; lk <= lp; lk++) {
-            const int64_t k = (int64_t)1 << lk;
-            for (int64_t t = threadIdx.x; t < half; t += BLK) {
-                const int64_t i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
-                const int64_t j = i ^ (k - 1);
-                if (j < len) {                          // j >= len holds a virtual all-ones key
-                    uint64_t x = a[i], y = a[j];
-                    if (y < x) { a[i] = y; a[j] = x; }
-                }
-            }
-            __threadfence_block();
-            __syncthreads();
-            for (int lj = lk - 2; lj >= 0; lj--) {
-                const int64_t j = (int64_t)1 << lj;
-                for (int64_t t = threadIdx.x; t < half; t += BLK) {
-                    const int64_t i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
-                    if (i + j < len) {
-                        uint64_t x = a[i], y = a[i + j];
-                        if (y < x) { a[i] = y; a[i + j] = x; }
+__global__ __launch_bounds__(BLKG) void k_sort_global(uint64_t* __restrict__ keys,
+                                                      const int64_t* __restrict__ off, int64_t nseg) {
+    __shared__ int64_t lst[BLKG];
+    __shared__ int cnt;
+    const int64_t G = gridDim.x;
+    for (int64_t i0 = 0; (int64_t)blockIdx.x + G * i0 < nseg; i0 += BLKG) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        {
+            const int64_t s = (int64_t)blockIdx.x + G * (i0 + threadIdx.x);
+            if (s < nseg && off[s + 1] - off[s] > LCAP) lst[atomicAdd(&cnt, 1)] = s;
+        }
+        __syncthreads();
+        const int c = cnt;
+        for (int q = 0; q < c; q++) {
+            const int64_t s = lst[q];
+            const int64_t b = off[s];
+            const int64_t len = off[s + 1] - b;
+            uint64_t* a = keys + b;
+            int lp = 0;
+            while (((int64_t)1 << lp) < len) lp++;
+            const int64_t half = (int64_t)1 << (lp - 1);
+            for (int lk = 1; lk <= lp; lk++) {
+                const int64_t k = (int64_t)1 << lk;
+                for (int64_t t = threadIdx.x; t < half; t += BLKG) {
+                    const int64_t i = ((t >> (lk - 1)) << lk) | (t & ((k >> 1) - 1));
+                    const int64_t j = i ^ (k - 1);
+                    if (j < len) {                          // j >= len holds a virtual all-ones key
+                        uint64_t x = a[i], y = a[j];
+                        if (y < x) { a[i] = y; a[j] = x; }
                     }
                 }
                 __threadfence_block();
                 __syncthreads();
+                for (int lj = lk - 2; lj >= 0; lj--) {
+                    const int64_t j = (int64_t)1 << lj;
+                    for (int64_t t = threadIdx.x; t < half; t += BLKG) {
+                        const int64_t i = ((t >> lj) << (lj + 1)) | (t & (j - 1));
+                        if (i + j < len) {
+                            uint64_t x = a[i], y = a[i + j];
+                            if (y < x) { a[i] = y; a[i + j] = x; }
+                        }
+                    }
+                    __threadfence_block();
+                    __syncthreads();
+                }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -169,7 +219,7 @@ int launch_segsort_u64(uint64_t* keys, const int64_t* off, int64_t nseg, int64_t
     if (nseg <= 0 || total <= 1) return 0;
     hipLaunchKernelGGL(k_sort_wave, dim3(grid_cap((nseg + 3) / 4)), dim3(BLK), 0, st, keys, off, nseg);
     hipLaunchKernelGGL(k_sort_lds, dim3(grid_cap(nseg < 2048 ? nseg : 2048)), dim3(BLKL), 0, st, keys, off, nseg);
-    hipLaunchKernelGGL(k_sort_global, dim3(grid_cap(nseg < 1024 ? nseg : 1024)), dim3(BLK), 0, st, keys, off, nseg);
+    hipLaunchKernelGGL(k_sort_global, dim3(grid_cap(nseg < 1024 ? nseg : 1024)), dim3(BLKG), 0, st, keys, off, nseg);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

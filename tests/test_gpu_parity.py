@@ -493,9 +493,23 @@ def test_hashed_root_distances(rank):
     order = c["order"] if rank == "degree" else gg.random_rank(c["n"], 5)
     _say("hashed root distances", rank)
     ref = oracle.chl(c["row_ptr"], c["col"], c["w"], order)
-    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], order, prune_hubs=4096)
+    # the batched kernel alone (not the small-tree kernel) grows the main phase
+    L, off, hub, dist = gpu_labels(c["row_ptr"], c["col"], c["w"], order, prune_hubs=4096, small=False)
     assert_same_labels(off, hub, dist, ref, "hashed " + rank)
     st = L.stats(per_root=True)
     assert st["prune_hubs"] == 4096
+    assert st["small_trees"] == 0
     assert np.array_equal(st["per_root"][:, 2], ref.stats[:, 2])
+    # both paths ran: a main-phase root's prefix labels are its labels of the
+    # hubs [0, 4096); the hash holds 512 of them (degree rank: at most 85
+    # each, all hashed; random rank: 7,688 of the 12,288 roots have more)
+    start = int(st["prefix_roots"])
+    assert start == 4096
+    cs = np.concatenate([[0], np.cumsum(ref.hub_pos < 4096)])
+    per_v = cs[ref.offsets[1:]] - cs[ref.offsets[:-1]]
+    over = int((per_v[np.asarray(order)[start:]] > 512).sum())
+    _say("main-phase roots beyond the hash: %d of %d" % (over, c["n"] - start))
+    assert over < c["n"] - start
+    if rank == "random":
+        assert over > 0
     L.free()
