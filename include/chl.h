@@ -120,9 +120,10 @@ typedef struct chl_build_opts {
     int32_t root_stride;     /* >= 1 when root_count > 0 */
     int32_t prune_hubs;      /* batched form: rank-prefix pruning (Section 4.3).
                                 The trees of roots [0, 16) grow first; each
-                                later level of roots [g, 8g) -- [g, 2g) after a
-                                level whose roots emitted >= 2^21 labels -- is
-                                pruned by the labels of the hubs [0, g)
+                                later level of roots [g, 8g) -- [g, 2g) and
+                                [g, 4g) in turn after levels whose roots
+                                emitted >= 2^21 labels -- is pruned by the
+                                labels of the hubs [0, g)
                                 (complete by then), up to a prefix of
                                 prune_hubs hubs (<= 8192); every other tree is
                                 pruned by that prefix. A relaxation is dropped

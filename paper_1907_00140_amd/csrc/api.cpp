@@ -206,7 +206,7 @@ struct Build {
 };
 
 // labels emitted by a pruning level above which the next level is only
-// twice as large (else eight times)
+// two or four times as large (else eight times)
 constexpr unsigned long long LEVEL_LABELS_X2 = 1ull << 21;
 
 size_t slot_bytes(int32_t n, int key_bits) {
@@ -885,18 +885,25 @@ static int run_levels(Arena& A, Build& B, const chl_build_opts& o, void* scan_tm
     }
     B.pbound = 0;
     if (keep) {
+        int32_t last_f = 0;
         while (g < gmax) {
             // a level whose trees emitted many labels did much work: grow
-            // the prefix by 2, so that the next level is pruned by more
-            // hubs; after a small level, whose time is the latency of its
-            // trees, grow by 8, to have fewer levels (the labels of a
+            // the prefix slowly, so that the next level is pruned by more
+            // hubs, by 2 and 4 in turn (every level also costs a regrouping
+            // of the table and a launch tail: on R-MAT 20, 2, 4, 2, 4, 2
+            // built 3.5% faster than 2 throughout; 4 throughout, or 4 first,
+            // was slower); after a small level, whose time is the latency of
+            // its trees, grow by 8, to have fewer levels (the labels of a
             // root do not depend on the schedule, so neither does the
             // schedule itself). The first pruned level of a directed build
             // grows by 4: its combined graph's second level [16, 128) ends
             // with a few large trees on small teams, and [16, 64) on teams
             // of 5 builds the directed R-MAT 16 5% faster (the undirected
             // R-MAT 16 is 7% slower that way)
-            const int32_t f = g == 16 && B.partner ? 4 : level_labels >= LEVEL_LABELS_X2 ? 2 : 8;
+            const int32_t f = g == 16 && B.partner ? 4
+                              : level_labels >= LEVEL_LABELS_X2 ? (last_f == 2 ? 4 : 2)
+                                                                : 8;
+            last_f = f;
             const int32_t g2 = std::min<int32_t>(gmax, f * g);
             B.pbound = g;
             TeamCfg tc;
@@ -1232,11 +1239,11 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     if (B.stats) HIPCHK(hipMemsetAsync(B.stats, 0, (size_t)n * STAT_COLS * 8, st));
 
     // ---- rank-prefix pruning (Section 4.3) in levels: the trees of roots
-    //      [0, 16) grow unpruned; then every level [g, 8g) (or [g, 2g), see
-    //      LEVEL_LABELS_X2) is pruned by the labels of the hubs [0, g), which
-    //      are complete, and so on up to the prefix size; the main phase is
-    //      pruned by the whole prefix. The labels of every level extend the
-    //      per-vertex groups of the levels before it.
+    //      [0, 16) grow unpruned; then every level [g, 8g) (or [g, 2g) and
+    //      [g, 4g) in turn, see LEVEL_LABELS_X2) is pruned by the labels of
+    //      the hubs [0, g), which are complete, and so on up to the prefix
+    //      size; the main phase is pruned by the whole prefix. The labels of
+    //      every level extend the per-vertex groups of the levels before it.
     int launches = 0;
     int prefix_launches = 0;
     double prune_ms = 0;

@@ -20,8 +20,9 @@ another schedule are never used by mistake.
 "16/0"); --schedule counts the pruned trees under that schedule; --default
 counts the schedule that the library's default build takes (the policy below
 mirrors the library's: roots [0, 16) first, then each level 8 times the
-prefix, or 2 times after a level whose roots emitted 2^21 labels or more, or
-4 times for the first pruned level of a directed build's combined graph, up
+prefix, or 2 and 4 times in turn after levels whose roots emitted 2^21 labels
+or more, or 4 times for the first pruned level of a directed build's combined
+graph, up
 to min(8192, max(64, n/64), n/2) hubs). Directed workloads are counted on
 their combined graph (the graph and its reversal, ranks interleaved), as the
 library builds them.
@@ -57,8 +58,15 @@ def level_bounds(labels_per_root, gmax, first=None):
     g = min(LEVEL0, gmax)
     lv = [g]
     lab = int(labels_per_root[0:g].sum())
+    last_f = 0
     while g < gmax:
-        f = first if first and g == LEVEL0 else (2 if lab >= LEVEL_LABELS_X2 else 8)
+        if first and g == LEVEL0:
+            f = first
+        elif lab >= LEVEL_LABELS_X2:
+            f = 4 if last_f == 2 else 2
+        else:
+            f = 8
+        last_f = f
         g2 = min(gmax, f * g)
         lab = int(labels_per_root[g:g2].sum())
         lv.append(g2)

@@ -168,8 +168,8 @@ def test_levels_equal_definition(lib, seed):
 
 def test_level_schedule_rule():
     """The pruning-level schedule the work counts use: roots [0, 16) first,
-    then a prefix 2x larger after a level whose roots emitted >= 2^21 labels,
-    else 8x larger, capped at the prefix size."""
+    then a prefix 2x and 4x larger in turn after levels whose roots emitted
+    >= 2^21 labels, else 8x larger, capped at the prefix size."""
     import importlib.util
     import os
     spec = importlib.util.spec_from_file_location(
@@ -181,6 +181,9 @@ def test_level_schedule_rule():
     lab[:16] = 200_000          # 3.2 M labels: work-bound level -> x2
     lab[16:32] = 100_000        # 1.6 M labels -> x8
     assert level_bounds(lab, 4096) == [16, 32, 256, 2048, 4096]
+    lab[16:32] = 200_000        # 3.2 M labels -> x4 after the x2
+    lab[32:128] = 30_000        # 2.9 M labels -> x2 after the x4
+    assert level_bounds(lab, 4096) == [16, 32, 128, 256, 2048, 4096]
     assert level_bounds(np.zeros(100, np.int64), 50) == [16, 50]
     assert level_bounds(np.zeros(100, np.int64), 8) == [8]
     # a directed build's first pruned level grows by 4
