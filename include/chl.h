@@ -376,7 +376,9 @@ typedef struct chl_stats {
 /* Totals into *totals (host, may be NULL). per_root (may be NULL) receives
  * int64[n][6] indexed by root rank position: vertex relaxations, arcs
  * relaxed, labels, stopped early (0/1), relaxation rounds, and the tree's
- * duration in device wall-clock ticks (batched form; 0 in the plain form);
+ * duration in device wall-clock ticks (batched form; 0 in the plain form
+ * and for a main-phase root without arcs, whose single label is written
+ * without growing a tree);
  * host or device as for chl_labels_export. Per-root data needs opts.stats=1,
  * otherwise CHL_ERR_INVALID_ARG is returned when per_root is not NULL. */
 int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root,

@@ -291,6 +291,46 @@ def test_edge_cases():
     assert q == [3, -1, 0, 2]
 
 
+@pytest.mark.parametrize("rank", ["degree", "random"])
+def test_arcless_roots(rank):
+    """A main-phase root without arcs gets its single label (r, r, 0) without
+    a tree: R-MAT 12 with 3000 isolated vertices added (under a random rank
+    spread over every level and the main phase, under the degree rank all in
+    the main phase). Labels and labels per root equal the oracle's; those
+    roots report one settled vertex, no arcs, one round and no tree time."""
+    c = gg.make_config("rmat12s9")
+    extra = 3000
+    row = np.concatenate([c["row_ptr"], np.full(extra, c["row_ptr"][-1], np.int64)])
+    n = len(row) - 1
+    order = gg.random_rank(n, 11) if rank == "random" else gg.degree_rank(row, 11)
+    _say("arcless roots", rank, n)
+    ref = oracle.chl(row, c["col"], c["w"], order)
+    L, off, hub, dist = gpu_labels(row, c["col"], c["w"], order)
+    assert_same_labels(off, hub, dist, ref, "arcless " + rank)
+    st = L.stats(per_root=True)
+    pr = st["per_root"]
+    assert np.array_equal(pr[:, 2], ref.stats[:, 2])
+    start = int(st["prefix_roots"])
+    arcless = np.diff(row)[np.asarray(order)][start:] == 0
+    assert arcless.sum() >= (extra if rank == "degree" else extra // 2)
+    m = pr[start:][arcless]
+    assert np.all(m[:, 0] == 1) and np.all(m[:, 1] == 0) and np.all(m[:, 4] == 1) and np.all(m[:, 5] == 0)
+    assert np.any(pr[start:][~arcless, 5] > 0)
+    L.free()
+    # no arcs at all: every root is its own tree
+    L = chl_build_empty(700)
+    off, hub, dist = (t.numpy() for t in L.export("cpu"))
+    assert np.array_equal(off, np.arange(701)) and np.array_equal(dist, np.zeros(700))
+    assert L.stats()["labels"] == 700
+    L.free()
+
+
+def chl_build_empty(n):
+    from paper_1907_00140_amd import chl
+    return chl.build(np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                     np.arange(n, dtype=np.int32)[::-1].copy())
+
+
 def test_distance_overflow():
     """A label distance of 2^31 - 1 or more is an error; just below is fine."""
     from paper_1907_00140_amd import chl
