@@ -1307,37 +1307,40 @@ static int chl_build_impl(const chl_graph* g, const int32_t* order, const chl_bu
     std::vector<int32_t> sel;
     if (o.root_count > 0)
         for (int32_t i = 0; i < o.root_count; i++) sel.push_back(o.root_begin + i * o.root_stride);
-    // The main phase of the batched form: a root without arcs is a tree of
-    // one vertex, clean, whose label (r, r, 0) is written directly; the tree
-    // kernels grow the other roots from a list (R-MAT 20: 501,961 of the
-    // 1,040,384 main-phase roots, a third of the phase's workgroup time as
-    // trees).
+    // The main phase of the batched form: a root without arcs, or one whose
+    // neighbours all outrank it, has the root alone as its tree (every other
+    // vertex is reached through an outranking neighbour), so its only label
+    // (r, r, 0) is written directly; the tree kernels grow the other roots
+    // from a list (R-MAT 20: 501,961 roots without arcs and 375,030 with
+    // outranking neighbours of the 1,040,384 main-phase roots).
     int32_t nmain = n - grown;
     bool listed = false;
     if (o.mode != CHL_MODE_PLAIN && o.hybrid_psi <= 0 && sel.empty() && nmain > 0) {
         int32_t* flag = A.get<int32_t>((size_t)nmain);
+        int32_t* one = A.get<int32_t>((size_t)nmain);
         int64_t* pos = A.get<int64_t>((size_t)nmain + 1);
         HostCtl* hc1 = host_ctl();
-        if (!flag || !pos) return CHL_ERR_OOM;
+        if (!flag || !one || !pos) return CHL_ERR_OOM;
         if (!hc1) return CHL_ERR_HIP;
-        if (launch_arcless_count(grown, nmain, B.g.row, flag, pos, scan_tmp, st)) return CHL_ERR_HIP;
+        if (launch_trivial_count(grown, nmain, B.g.row, B.g.arc, flag, one, pos, scan_tmp, st)) return CHL_ERR_HIP;
         HIPCHK(hipMemcpyAsync(hc1->c64, pos + nmain, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        const unsigned long long narcless = hc1->c64[0];
-        if (narcless > 0) {
+        const unsigned long long ntrivial = hc1->c64[0];
+        if (ntrivial > 0) {
             const unsigned long long base = B.cursor_base;
-            if (base + narcless > B.pool.cap)
-                if (int r0 = grow_pool(A, B, base, base + narcless, st)) return r0;
-            if (launch_arcless_split(grown, nmain, flag, pos, B.pool, base, B.roots, B.stats, st))
+            if (base + ntrivial > B.pool.cap)
+                if (int r0 = grow_pool(A, B, base, base + ntrivial, st)) return r0;
+            if (launch_trivial_split(grown, nmain, flag, pos, B.pool, base, B.roots, B.stats, st))
                 return CHL_ERR_HIP;
-            hc1->c64[1] = base + narcless;
+            hc1->c64[1] = base + ntrivial;
             HIPCHK(hipMemcpyAsync(B.ctl64, &hc1->c64[1], 8, hipMemcpyHostToDevice, st));
             HIPCHK(hipStreamSynchronize(st));
-            B.last_used = base + narcless;
-            nmain -= (int32_t)narcless;
+            B.last_used = base + ntrivial;
+            nmain -= (int32_t)ntrivial;
             listed = true;
         }
         A.drop(flag);
+        A.drop(one);
         A.drop(pos);
     }
     int r = o.mode == CHL_MODE_PLAIN

@@ -105,18 +105,31 @@ int launch_stat_sums(int32_t n, const int64_t* stats, int64_t* sums, hipStream_t
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Roots without arcs among the rank positions [lo, lo + cnt). Growing the
-// tree of such a root (Algorithm 3) settles the root alone, clean, so its
-// only label is (r, r, 0): flag[i] = 1 marks them, and after the scan
-// k_arcless_split writes their labels to the pool (from entry base on, in
-// rank order) and their statistics rows, and lists the other roots, in rank
-// order, for the tree kernels.
-__global__ void k_arcless_flags(int32_t lo, int32_t cnt, const int64_t* __restrict__ row, int32_t* __restrict__ flag) {
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
-        flag[i] = row[(int64_t)lo + i + 1] == row[(int64_t)lo + i] ? 1 : 0;
+// Roots among the rank positions [lo, lo + cnt) whose tree is the root
+// alone. A root r without arcs settles only itself; a root all of whose
+// neighbours outrank it (rank positions below r: the last arc of r's row,
+// sorted by target, has a smaller target) reaches every other vertex
+// through a neighbour that outranks it, so Algorithm 3 flags every vertex
+// but r and the tree stops at once. Either way r's only label is (r, r, 0):
+// flag[i] = 1 (no arcs) or 2 (neighbours all outrank r) marks them, and
+// after the scan k_trivial_split writes their labels to the pool (from entry
+// base on, in rank order) and their statistics rows, and lists the other
+// roots, in rank order, for the tree kernels.
+__global__ void k_trivial_flags(int32_t lo, int32_t cnt, const int64_t* __restrict__ row,
+                                const uint64_t* __restrict__ arc, int32_t* __restrict__ flag) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x) {
+        const int32_t r = lo + i;
+        const int64_t b = row[r], e = row[(int64_t)r + 1];
+        flag[i] = b == e ? 1 : (int32_t)(arc[e - 1] >> 32) < r ? 2 : 0;
+    }
 }
 
-__global__ void k_arcless_split(int32_t lo, int32_t cnt, const int32_t* __restrict__ flag,
+__global__ void k_trivial_mark(int32_t cnt, const int32_t* __restrict__ flag, int32_t* __restrict__ one) {
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gridDim.x * blockDim.x)
+        one[i] = flag[i] != 0 ? 1 : 0;
+}
+
+__global__ void k_trivial_split(int32_t lo, int32_t cnt, const int32_t* __restrict__ flag,
                                 const int64_t* __restrict__ pos, int32_t* __restrict__ pv, int32_t* __restrict__ ph,
                                 int32_t* __restrict__ pd, uint64_t base, int32_t* __restrict__ roots,
                                 int64_t* __restrict__ stats) {
@@ -128,12 +141,13 @@ __global__ void k_arcless_split(int32_t lo, int32_t cnt, const int32_t* __restri
             ph[base + q] = r;
             pd[base + q] = 0;
             if (stats) {
-                // settled, arcs, labels, stopped early, rounds, ticks
+                // settled, arcs relaxed (none), labels, stopped early (with
+                // its outranking neighbours queued, flagged), rounds, ticks
                 int64_t* sr = stats + (int64_t)r * STAT_COLS;
                 sr[0] = 1;
                 sr[1] = 0;
                 sr[2] = 1;
-                sr[3] = 0;
+                sr[3] = flag[i] == 2 ? 1 : 0;
                 sr[4] = 1;
                 sr[5] = 0;
             }
@@ -143,20 +157,21 @@ __global__ void k_arcless_split(int32_t lo, int32_t cnt, const int32_t* __restri
     }
 }
 
-int launch_arcless_count(int32_t lo, int32_t cnt, const int64_t* row, int32_t* flag, int64_t* pos, void* scan_temp,
-                         hipStream_t st) {
+int launch_trivial_count(int32_t lo, int32_t cnt, const int64_t* row, const uint64_t* arc, int32_t* flag,
+                         int32_t* one, int64_t* pos, void* scan_temp, hipStream_t st) {
     if (cnt <= 0) return 0;
     const int blocks = (int)std::min<int64_t>(4096, ((int64_t)cnt + 255) / 256);
-    hipLaunchKernelGGL(k_arcless_flags, dim3(blocks), dim3(256), 0, st, lo, cnt, row, flag);
+    hipLaunchKernelGGL(k_trivial_flags, dim3(blocks), dim3(256), 0, st, lo, cnt, row, arc, flag);
+    hipLaunchKernelGGL(k_trivial_mark, dim3(blocks), dim3(256), 0, st, cnt, flag, one);
     if (hipGetLastError() != hipSuccess) return -1;
-    return launch_scan_i32_to_i64(flag, pos, cnt, scan_temp, st);
+    return launch_scan_i32_to_i64(one, pos, cnt, scan_temp, st);
 }
 
-int launch_arcless_split(int32_t lo, int32_t cnt, const int32_t* flag, const int64_t* pos, const Pool& pool,
+int launch_trivial_split(int32_t lo, int32_t cnt, const int32_t* flag, const int64_t* pos, const Pool& pool,
                          uint64_t base, int32_t* roots, int64_t* stats, hipStream_t st) {
     if (cnt <= 0) return 0;
     const int blocks = (int)std::min<int64_t>(4096, ((int64_t)cnt + 255) / 256);
-    hipLaunchKernelGGL(k_arcless_split, dim3(blocks), dim3(256), 0, st, lo, cnt, flag, pos, pool.v, pool.hub,
+    hipLaunchKernelGGL(k_trivial_split, dim3(blocks), dim3(256), 0, st, lo, cnt, flag, pos, pool.v, pool.hub,
                        pool.dist, base, roots, stats);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

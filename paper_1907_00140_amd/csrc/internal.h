@@ -220,14 +220,15 @@ int launch_swap_halves(const uint64_t* in, uint64_t* out, uint64_t total, hipStr
 // assemble.hip: count[v] = size of v's group in off (0 for every v when
 // off is NULL): the running sizes that launch_prefix_extend continues from
 int launch_group_sizes(int32_t n, const int64_t* off, int32_t* count, hipStream_t st);
-// roots without arcs among the rank positions [lo, lo + cnt): flag[i] = 1 for
-// them, pos = exclusive prefix sums of flag (pos[cnt] = their number); then
-// their single labels (r, r, 0) go to the pool entries [base, base + pos[cnt]),
-// their statistics rows to stats (if not NULL), and the other roots, in rank
-// order, to roots[0, cnt - pos[cnt])
-int launch_arcless_count(int32_t lo, int32_t cnt, const int64_t* row, int32_t* flag, int64_t* pos, void* scan_temp,
-                         hipStream_t st);
-int launch_arcless_split(int32_t lo, int32_t cnt, const int32_t* flag, const int64_t* pos, const Pool& pool,
+// roots among the rank positions [lo, lo + cnt) whose tree is the root alone
+// (no arcs: flag[i] = 1; every neighbour outranks it: 2; else 0), one[i] =
+// flag[i] != 0, pos = exclusive prefix sums of one (pos[cnt] = their
+// number); then their single labels (r, r, 0) go to the pool entries
+// [base, base + pos[cnt]), their statistics rows to stats (if not NULL), and
+// the other roots, in rank order, to roots[0, cnt - pos[cnt])
+int launch_trivial_count(int32_t lo, int32_t cnt, const int64_t* row, const uint64_t* arc, int32_t* flag,
+                         int32_t* one, int64_t* pos, void* scan_temp, hipStream_t st);
+int launch_trivial_split(int32_t lo, int32_t cnt, const int32_t* flag, const int64_t* pos, const Pool& pool,
                          uint64_t base, int32_t* roots, int64_t* stats, hipStream_t st);
 // hybrid.hip: the cleaning query DQ_Clean (Algorithm 2) over the labels of
 // the roots [lo, hi), whose pool ranges rlab holds (first entry, count per

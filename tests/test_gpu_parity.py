@@ -292,30 +292,43 @@ def test_edge_cases():
 
 
 @pytest.mark.parametrize("rank", ["degree", "random"])
-def test_arcless_roots(rank):
-    """A main-phase root without arcs gets its single label (r, r, 0) without
-    a tree: R-MAT 12 with 3000 isolated vertices added (under a random rank
-    spread over every level and the main phase, under the degree rank all in
-    the main phase). Labels and labels per root equal the oracle's; those
-    roots report one settled vertex, no arcs, one round and no tree time."""
+def test_trivial_roots(rank):
+    """A main-phase root whose tree is the root alone (no arcs, or every
+    neighbour outranks it) gets its single label (r, r, 0) without a tree:
+    R-MAT 12 with 3000 isolated vertices added (under a random rank spread
+    over every level and the main phase, under the degree rank all in the
+    main phase). Labels and labels per root equal the oracle's; those roots
+    report one settled vertex, no arcs relaxed, one round and no tree time,
+    and the others were grown by the tree kernels."""
     c = gg.make_config("rmat12s9")
     extra = 3000
     row = np.concatenate([c["row_ptr"], np.full(extra, c["row_ptr"][-1], np.int64)])
     n = len(row) - 1
-    order = gg.random_rank(n, 11) if rank == "random" else gg.degree_rank(row, 11)
-    _say("arcless roots", rank, n)
+    order = np.asarray(gg.random_rank(n, 11) if rank == "random" else gg.degree_rank(row, 11))
+    _say("trivial roots", rank, n)
     ref = oracle.chl(row, c["col"], c["w"], order)
     L, off, hub, dist = gpu_labels(row, c["col"], c["w"], order)
-    assert_same_labels(off, hub, dist, ref, "arcless " + rank)
+    assert_same_labels(off, hub, dist, ref, "trivial " + rank)
     st = L.stats(per_root=True)
     pr = st["per_root"]
     assert np.array_equal(pr[:, 2], ref.stats[:, 2])
     start = int(st["prefix_roots"])
-    arcless = np.diff(row)[np.asarray(order)][start:] == 0
-    assert arcless.sum() >= (extra if rank == "degree" else extra // 2)
-    m = pr[start:][arcless]
-    assert np.all(m[:, 0] == 1) and np.all(m[:, 1] == 0) and np.all(m[:, 4] == 1) and np.all(m[:, 5] == 0)
-    assert np.any(pr[start:][~arcless, 5] > 0)
+    # by rank position: no arcs, or the largest neighbour position below its own
+    pos = np.empty(n, np.int64)
+    pos[order] = np.arange(n)
+    deg = np.diff(row)
+    top = np.full(n, -1, np.int64)
+    np.maximum.at(top, np.repeat(np.arange(n), deg), pos[c["col"]])
+    arcless = (deg == 0)[order][start:]
+    outranked = ((deg > 0) & (top < pos))[order][start:]
+    _say("main-phase roots", n - start, "without arcs", int(arcless.sum()), "outranked", int(outranked.sum()))
+    assert arcless.sum() >= (extra if rank == "degree" else extra // 2) and outranked.sum() > 0
+    trivial = arcless | outranked
+    m = pr[start:][trivial]
+    assert np.all(m[:, 0] == 1) and np.all(m[:, 1] == 0) and np.all(m[:, 2] == 1)
+    assert np.all(m[:, 4] == 1) and np.all(m[:, 5] == 0)
+    assert np.array_equal(pr[start:][outranked, 3], np.ones(int(outranked.sum()), np.int64))
+    assert np.all(pr[start:][~trivial, 5] > 0)
     L.free()
     # no arcs at all: every root is its own tree
     L = chl_build_empty(700)
