@@ -379,7 +379,7 @@ typedef struct chl_stats {
  * duration in device wall-clock ticks (batched form; 0 in the plain form
  * and for a main-phase root whose tree is the root alone -- no arcs, or
  * every neighbour outranks it -- whose single label is written without
- * growing a tree, and whose arcs count is then 0);
+ * growing a tree, and whose arcs and stopped-early entries are then 0);
  * host or device as for chl_labels_export. Per-root data needs opts.stats=1,
  * otherwise CHL_ERR_INVALID_ARG is returned when per_root is not NULL. */
 int chl_build_stats(const chl_labels* h, chl_stats* totals, int64_t* per_root,

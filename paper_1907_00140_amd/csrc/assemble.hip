@@ -141,13 +141,13 @@ __global__ void k_trivial_split(int32_t lo, int32_t cnt, const int32_t* __restri
             ph[base + q] = r;
             pd[base + q] = 0;
             if (stats) {
-                // settled, arcs relaxed (none), labels, stopped early (with
-                // its outranking neighbours queued, flagged), rounds, ticks
+                // settled, arcs relaxed, labels, stopped early (no tree was
+                // grown, so none), rounds, ticks
                 int64_t* sr = stats + (int64_t)r * STAT_COLS;
                 sr[0] = 1;
                 sr[1] = 0;
                 sr[2] = 1;
-                sr[3] = flag[i] == 2 ? 1 : 0;
+                sr[3] = 0;
                 sr[4] = 1;
                 sr[5] = 0;
             }

@@ -298,8 +298,8 @@ def test_trivial_roots(rank):
     R-MAT 12 with 3000 isolated vertices added (under a random rank spread
     over every level and the main phase, under the degree rank all in the
     main phase). Labels and labels per root equal the oracle's; those roots
-    report one settled vertex, no arcs relaxed, one round and no tree time,
-    and the others were grown by the tree kernels."""
+    report one settled vertex, no arcs relaxed, no early stop, one round and
+    no tree time, and the others were grown by the tree kernels."""
     c = gg.make_config("rmat12s9")
     extra = 3000
     row = np.concatenate([c["row_ptr"], np.full(extra, c["row_ptr"][-1], np.int64)])
@@ -326,8 +326,7 @@ def test_trivial_roots(rank):
     trivial = arcless | outranked
     m = pr[start:][trivial]
     assert np.all(m[:, 0] == 1) and np.all(m[:, 1] == 0) and np.all(m[:, 2] == 1)
-    assert np.all(m[:, 4] == 1) and np.all(m[:, 5] == 0)
-    assert np.array_equal(pr[start:][outranked, 3], np.ones(int(outranked.sum()), np.int64))
+    assert np.all(m[:, 3] == 0) and np.all(m[:, 4] == 1) and np.all(m[:, 5] == 0)
     assert np.all(pr[start:][~trivial, 5] > 0)
     L.free()
     # no arcs at all: every root is its own tree
