@@ -396,8 +396,8 @@ int chl_server_create(const chl_server_opts* o, const chl_allocator* alloc, chl_
     // serves a build's temporaries from memory freed by earlier builds. No
     // memory is reserved up front: the pool was measured to keep at most
     // about 0.75 GB of freed memory whatever its release threshold, so
-    // taking the budget from the driver here and freeing it into the pool
-    // only moved it through the driver and back.
+    // allocating the budget here and freeing it into the pool only mapped
+    // device memory and handed it straight back to the system.
     bool ok = hipStreamCreateWithFlags(&s->qs, hipStreamNonBlocking) == hipSuccess;
     for (int i = 0; i < so.build_streams && ok; i++) {
         hipStream_t st;
